@@ -1,0 +1,272 @@
+/*
+ * fc.h -- C ABI of libfactory_sdf.so: vertex-vs-SDF contact queries, contact
+ * reduction and the penetration-penalty adjoint on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Narang et al., "Factory: Fast Contact for Robotic Assembly",
+ * RSS 2022):
+ *   - Section III-A: body B is a signed distance field sampled on a voxel
+ *     grid and read with trilinear filtering; its value and gradient give a
+ *     contact's distance and normal.
+ *   - Section III-B: a contact is a point, a normal and a distance (7 floats)
+ *     plus the two body indices.
+ *   - Section III-C, Algorithm 1: for each shape pair, Generate candidate
+ *     contacts for the mesh body queried against the SDF body, then reduce
+ *     them: FindDeepest keeps the deepest candidate and BinReduce gathers the
+ *     candidates of similar normal.  Here the patches are fixed
+ *     normal-direction bins: per (environment, bin) the deepest candidate is
+ *     kept, ties going to the lowest vertex index.
+ *   - Appendix, Robot Learning Tools, "Using Contact Simulation Methods":
+ *     when both bodies carry an SDF, the body with more triangles is the SDF
+ *     and the other one's mesh is queried against it.  Here body A is always the queried mesh and
+ *     body B the SDF.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named "device" are device memory owned by the caller; the
+ *     library never frees them and keeps no reference past the call, except
+ *     that a batch keeps the grid and mesh pointers given to fc_batch_create
+ *     and reads them on every call (they must outlive the batch).
+ *   - Pointers named "host" are read during the call only.
+ *   - Every compute call is asynchronous on `stream` (a hipStream_t passed as
+ *     void*; NULL = the default stream).  No compute call allocates, frees or
+ *     synchronises.  fc_batch_create / fc_batch_set_launch / fc_graph_create
+ *     allocate and synchronise (set-up calls).
+ *   - Arguments are validated completely before anything is launched; on an
+ *     error nothing is written and the status says why.  No call aborts,
+ *     throws or prints.  FC_ERR_HIP carries the HIP error in
+ *     fc_last_hip_error() (per thread).
+ *   - Units are metres.  Poses place A in B's frame.  All outputs are in B's
+ *     frame.
+ */
+#ifndef FACTORY_SDF_FC_H
+#define FACTORY_SDF_FC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fc_status {
+  FC_OK = 0,
+  FC_ERR_NULL = 1,        /* a required pointer is NULL */
+  FC_ERR_SHAPE = 2,       /* a size or count is out of range or inconsistent */
+  FC_ERR_DTYPE = 3,       /* unknown dtype or layout, or mixed within a batch */
+  FC_ERR_RANGE = 4,       /* a numeric parameter is out of range (h, k, K) */
+  FC_ERR_WORKSPACE = 5,   /* workspace NULL or smaller than fc_workspace_bytes */
+  FC_ERR_HIP = 6,         /* a HIP runtime call failed; see fc_last_hip_error */
+  FC_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+} fc_status;
+
+typedef enum fc_dtype { FC_F32 = 0, FC_F16 = 1, FC_BF16 = 2 } fc_dtype;
+
+/* FC_LAYOUT_LINEAR: samples [nz][ny][nx], x fastest.
+ * FC_LAYOUT_BRICK:  the same samples re-laid out by fc_grid_to_bricks into
+ *                   bricks of 4x4x4 nodes covering 3x3x3 cells (neighbouring
+ *                   bricks share their face nodes), so the 8 corners of any
+ *                   cell lie in one brick.  Values are copied, not rounded. */
+typedef enum fc_layout { FC_LAYOUT_LINEAR = 0, FC_LAYOUT_BRICK = 1 } fc_layout;
+
+#define FC_MAX_TYPES 8 /* distinct grids and distinct meshes per batch */
+#define FC_MAX_BINS 64 /* normal bins K */
+
+/* Body B: a voxel SDF (Section III-A).  Node (i,j,k) sits at
+ * origin + h*(i,j,k); values are node samples (node-centred, no half-voxel
+ * offset).  A point is inside the grid iff 0 <= (x-origin)/h <= n-1 on every
+ * axis; outside points are never candidates. */
+typedef struct fc_grid {
+  const void* data; /* device; fc_dtype samples; FP16/BF16 are IEEE half / bfloat16 bits */
+  int32_t dtype;    /* fc_dtype */
+  int32_t layout;   /* fc_layout */
+  int32_t nx, ny, nz; /* nodes per axis, each >= 2, nx*ny*nz < 2^31 */
+  float origin[3];  /* node (0,0,0), metres */
+  float h;          /* node spacing, > 0, metres */
+} fc_grid;
+
+/* Body A: the queried mesh's vertices in A's frame, SoA (device). */
+typedef struct fc_mesh {
+  const float* x;
+  const float* y;
+  const float* z;
+  int32_t n_verts; /* >= 0 (an empty mesh gives empty contact lists) */
+} fc_mesh;
+
+/* Static description of a batch of independent environments (shape pairs).
+ * Environment e pairs grid env_grid[e] with mesh env_mesh[e]; its query index
+ * is q = qoff[e] + v for vertex v, qoff[e] = sum of n_verts over envs < e. */
+typedef struct fc_batch_desc {
+  int32_t n_env;            /* >= 1 */
+  const fc_grid* grids;     /* host [n_grids], 1 <= n_grids <= FC_MAX_TYPES; one dtype and layout */
+  int32_t n_grids;
+  const fc_mesh* meshes;    /* host [n_meshes], 1 <= n_meshes <= FC_MAX_TYPES */
+  int32_t n_meshes;
+  const int32_t* env_grid;  /* host [n_env] in [0, n_grids), or NULL = all 0 */
+  const int32_t* env_mesh;  /* host [n_env] in [0, n_meshes), or NULL = all 0 */
+  int32_t n_bins;           /* K, 1 <= K <= FC_MAX_BINS */
+  const float* bin_dirs;    /* host [3][K] unit directions d_k (copied) */
+  float margin;             /* a query is a candidate iff phi < margin */
+} fc_batch_desc;
+
+typedef struct fc_batch fc_batch; /* opaque; owns device work tables */
+
+/* Per-query candidates (Algorithm 1, Generate), all device, index q:
+ *   phi[q]      trilinear SDF value at x_B, or +inf when x_B is outside the grid;
+ *   normal      [3][Q]: grad(phi)/|grad(phi)|, (0,0,0) for a zero gradient or outside;
+ *   bin[q]      argmax_k normal.d_k (lowest k on ties) when phi < margin, else -1. */
+typedef struct fc_candidates {
+  float* phi;
+  float* normal;
+  int16_t* bin;
+} fc_candidates;
+
+/* Reduced contacts, one slot per (environment, bin), slot s = e*K + k (device).
+ * Section III-B record: the point, normal and distance of the winner.
+ *   vidx[s]   winning vertex index in env e's mesh, -1 if the bin is empty;
+ *   depth[s]  -phi of the winner (+0.0 for -0.0), 0 if empty;
+ *   point     [3][n_env*K] x_B of the winner, 0 if empty;
+ *   normal    [3][n_env*K] unit normal of the winner, 0 if empty;
+ *   count[e]  number of non-empty bins of env e. */
+typedef struct fc_contacts {
+  int32_t* vidx;
+  float* depth;
+  float* point;
+  float* normal;
+  int32_t* count;
+} fc_contacts;
+
+/* Penetration-penalty outputs (device; each pointer may be NULL = not wanted).
+ *   loss[e]    L_e = sum over vertices with phi(x_B) < 0 of 0.5 k phi^2;
+ *   d_pose     [6][n_env]: g_e * dL_e/dxi at xi = 0 for the left twist
+ *              T <- exp(xi^) T, xi = (rho, omega): (sum w, sum x_B x w),
+ *              w = k phi grad(phi);
+ *   d_verts    verts_per_env == 0: per mesh m a block [3][n_verts(m)] of
+ *              sum over envs e of mesh m of g_e R_e^T w (blocks in mesh
+ *              order; summed in a fixed env order, bit-reproducible);
+ *              verts_per_env != 0: [3][Q], g_e R_e^T w per query q.
+ * g_e is upstream[e] (1 when upstream is NULL).  Sums are FP32 with
+ * compensated (Neumaier) accumulation in a fixed order; no FP64. */
+typedef struct fc_grads {
+  float* loss;
+  float* d_pose;
+  float* d_verts;
+  int32_t verts_per_env;
+} fc_grads;
+
+/* Launch shape of the query kernels (what the autotuner varies; results are
+ * bit-identical for every valid choice).
+ *   block       threads per workgroup: 128, 256 or 512;
+ *   tile        vertices per work item: block, 2*block or 4*block;
+ *   persistent  0: one workgroup per item; 1: a grid of about
+ *               grid_mult workgroups per compute unit pulling items in a
+ *               fixed order; 2: the same pulling items from an atomic counter;
+ *   grid_mult   workgroups per compute unit for persistent launches (1..32). */
+typedef struct fc_launch {
+  int32_t block;
+  int32_t tile;
+  int32_t persistent;
+  int32_t grid_mult;
+} fc_launch;
+
+/* ---- set-up ------------------------------------------------------------- */
+
+/* Validate the description and build the batch: device copies of the item
+ * and environment tables, and a default launch shape (or the one a loaded
+ * autotune cache gives for this batch's signature).  Errors: FC_ERR_NULL,
+ * FC_ERR_SHAPE, FC_ERR_DTYPE, FC_ERR_RANGE, FC_ERR_HIP. */
+fc_status fc_batch_create(const fc_batch_desc* desc, fc_batch** out);
+void fc_batch_destroy(fc_batch* batch); /* NULL is a no-op; synchronises */
+
+/* Q = total number of queries (sum of n_verts over envs); -1 for NULL. */
+int64_t fc_batch_queries(const fc_batch* batch);
+
+/* Replace the launch shape of the forward kernels (rebuilds the item table).
+ * FC_ERR_RANGE for an invalid shape. */
+fc_status fc_batch_set_launch(fc_batch* batch, const fc_launch* launch);
+fc_status fc_batch_get_launch(const fc_batch* batch, fc_launch* out);
+
+/* Workspace: device scratch the caller allocates once per batch, at least
+ * fc_workspace_bytes(batch) bytes, 256-byte aligned, ZERO-FILLED before its
+ * first use (fc_workspace_init, or any zero fill).  It holds the per-bin
+ * reduction keys and a work counter, which every call leaves at zero when it
+ * completes, and the adjoint's partial sums, which every call overwrites; so
+ * it can be reused, and captured in a graph, without clearing.  Calls that
+ * share a workspace must be ordered on one stream.  After a failed or
+ * interrupted launch, zero it again. */
+size_t fc_workspace_bytes(const fc_batch* batch);
+fc_status fc_workspace_init(const fc_batch* batch, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- compute (Section III-C, Algorithm 1) ------------------------------- */
+
+/* Generate: for every environment e and vertex v, x_B = R(q_e) v + t_e
+ * (R from the quaternion q = (x,y,z,w) as I + 2w[v]x + 2[v]x^2, not
+ * renormalised), then the trilinear SDF value and its exact gradient in the
+ * cell min(floor(u), n-2), a candidate iff phi < margin, its normal and bin.
+ *   pose       device [7][n_env]: qx,qy,qz,qw,tx,ty,tz (float32);
+ *   cand       NULL, or per-query candidates (written for every q);
+ *   fused_out  NULL, or reduced contacts: the reduction of
+ *              fc_contact_reduce fused into the same kernel (one launch;
+ *              candidates stay on chip).
+ * At least one of cand / fused_out must be non-NULL (else FC_ERR_NULL). */
+fc_status fc_sdf_query(const fc_batch* batch, const float* pose, const fc_candidates* cand,
+                       const fc_contacts* fused_out, void* ws, size_t ws_bytes, void* stream);
+
+/* FindDeepest / BinReduce over candidates written by fc_sdf_query with the
+ * same batch and pose: per (env, bin) the candidate of greatest depth, equal
+ * depths to the lowest vertex index.  The winner's point is recomputed from
+ * pose and vertex; its normal is read from cand.  Bit-identical to the fused
+ * form. */
+fc_status fc_contact_reduce(const fc_batch* batch, const float* pose, const fc_candidates* cand,
+                            const fc_contacts* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of the penetration penalty (see fc_grads): recomputes every query
+ * (same arithmetic as fc_sdf_query) and accumulates loss and gradients.
+ *   k          penalty stiffness, finite and > 0;
+ *   upstream   device [n_env] or NULL (all ones).
+ * At least one output pointer must be non-NULL. */
+fc_status fc_sdf_query_backward(const fc_batch* batch, const float* pose, float k, const float* upstream,
+                                const fc_grads* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- graphs ------------------------------------------------------------- */
+
+typedef struct fc_graph fc_graph; /* opaque instantiated hipGraph */
+
+/* Capture one step -- the fused forward (if fused_out) and the backward (if
+ * grads) -- into an instantiated hipGraph on a private capture stream.  The
+ * graph replays with the pointers given here.  Validation as for the calls. */
+fc_status fc_graph_create(const fc_batch* batch, const float* pose, const fc_contacts* fused_out, float k,
+                          const float* upstream, const fc_grads* grads, void* ws, size_t ws_bytes,
+                          fc_graph** out);
+fc_status fc_graph_launch(fc_graph* graph, void* stream);
+void fc_graph_destroy(fc_graph* graph);
+
+/* ---- layout conversion -------------------------------------------------- */
+
+/* Bytes of the brick layout of `src` (same dtype); 0 on invalid input. */
+size_t fc_grid_brick_bytes(const fc_grid* src);
+
+/* Re-lay out a linear grid into bricks: writes dst_data (device,
+ * fc_grid_brick_bytes bytes) and fills *dst with a descriptor of the result.
+ * Exact copy of the values (no rounding). */
+fc_status fc_grid_to_bricks(const fc_grid* src, void* dst_data, size_t dst_bytes, fc_grid* dst, void* stream);
+
+/* ---- autotuning and diagnostics ----------------------------------------- */
+
+/* Load a launch-shape cache written by the autotuner: a JSON object
+ * {"entries": [{"key": "<signature>", "block": B, "tile": T,
+ * "persistent": P, "grid_mult": M}, ...]}.  Batches created afterwards whose
+ * signature matches use that shape.  Returns the number of entries loaded,
+ * or -1 if the file cannot be read or parsed. */
+int32_t fc_autotune_load(const char* json_path);
+
+/* Signature of a batch, the autotune cache key (NUL-terminated, at most
+ * cap bytes written). Returns the full length, or -1 for NULL. */
+int32_t fc_batch_signature(const fc_batch* batch, char* buf, int32_t cap);
+
+const char* fc_status_str(fc_status status);
+int32_t fc_last_hip_error(void); /* hipError_t of the last FC_ERR_HIP on this thread */
+const char* fc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FACTORY_SDF_FC_H */

@@ -1,0 +1,795 @@
+// Host side of libfactory_sdf.so: argument validation, work tables, workspace
+// layout, launch selection, graph capture, brick conversion and the autotune
+// cache.  Declarations and their contracts are in include/fc.h.
+#include <hip/hip_runtime.h>
+
+#include <cctype>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fc_internal.h"
+
+using namespace fcimpl;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+fc_status hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return FC_ERR_HIP;
+}
+
+#define FC_HIP(x)                              \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+std::mutex g_tune_mu;
+std::map<std::string, fc_launch> g_tune;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool finitef(float x) { return std::isfinite(x); }
+
+int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+void bricks_of(const fc_grid& g, int& bx, int& by, int& bz) {
+  bx = ceil_div(g.nx - 1, kBrickCells);
+  by = ceil_div(g.ny - 1, kBrickCells);
+  bz = ceil_div(g.nz - 1, kBrickCells);
+}
+
+int elem_size(int dtype) { return dtype == FC_F32 ? 4 : 2; }
+
+fc_status check_grid(const fc_grid& g) {
+  if (!g.data) return FC_ERR_NULL;
+  if (g.dtype < FC_F32 || g.dtype > FC_BF16) return FC_ERR_DTYPE;
+  if (g.layout != FC_LAYOUT_LINEAR && g.layout != FC_LAYOUT_BRICK) return FC_ERR_DTYPE;
+  if (g.nx < 2 || g.ny < 2 || g.nz < 2) return FC_ERR_SHAPE;
+  if ((long long)g.nx * g.ny * g.nz >= (1LL << 31)) return FC_ERR_SHAPE;
+  if (g.layout == FC_LAYOUT_BRICK) {
+    int bx, by, bz;
+    bricks_of(g, bx, by, bz);
+    if ((long long)bx * by * bz * 64 >= (1LL << 31)) return FC_ERR_SHAPE;
+  }
+  if (!(g.h > 0.f) || !finitef(g.h) || !finitef(1.f / g.h)) return FC_ERR_RANGE;
+  for (int a = 0; a < 3; ++a)
+    if (!finitef(g.origin[a])) return FC_ERR_RANGE;
+  return FC_OK;
+}
+
+fc_status validate_desc(const fc_batch_desc* d) {
+  if (!d) return FC_ERR_NULL;
+  if (!d->grids || !d->meshes || !d->bin_dirs) return FC_ERR_NULL;
+  if (d->n_env < 1) return FC_ERR_SHAPE;
+  if (d->n_grids < 1 || d->n_grids > FC_MAX_TYPES) return FC_ERR_SHAPE;
+  if (d->n_meshes < 1 || d->n_meshes > FC_MAX_TYPES) return FC_ERR_SHAPE;
+  if (d->n_bins < 1 || d->n_bins > FC_MAX_BINS) return FC_ERR_RANGE;
+  if (!finitef(d->margin)) return FC_ERR_RANGE;
+  for (int i = 0; i < 3 * d->n_bins; ++i)
+    if (!finitef(d->bin_dirs[i])) return FC_ERR_RANGE;
+  for (int i = 0; i < d->n_grids; ++i) {
+    fc_status s = check_grid(d->grids[i]);
+    if (s != FC_OK) return s;
+    if (d->grids[i].dtype != d->grids[0].dtype || d->grids[i].layout != d->grids[0].layout) return FC_ERR_DTYPE;
+  }
+  for (int i = 0; i < d->n_meshes; ++i) {
+    const fc_mesh& m = d->meshes[i];
+    if (m.n_verts < 0) return FC_ERR_SHAPE;
+    if (m.n_verts > 0 && (!m.x || !m.y || !m.z)) return FC_ERR_NULL;
+  }
+  long long Q = 0;
+  for (int e = 0; e < d->n_env; ++e) {
+    const int gi = d->env_grid ? d->env_grid[e] : 0;
+    const int mi = d->env_mesh ? d->env_mesh[e] : 0;
+    if (gi < 0 || gi >= d->n_grids || mi < 0 || mi >= d->n_meshes) return FC_ERR_SHAPE;
+    Q += d->meshes[mi].n_verts;
+  }
+  if (Q >= (1LL << 40)) return FC_ERR_SHAPE;
+  return FC_OK;
+}
+
+bool launch_valid(const fc_launch& l) {
+  if (l.block <= 0 || l.tile <= 0 || l.tile % l.block) return false;
+  if (!forward_shape_supported(l.block, l.tile / l.block)) return false;
+  if (l.persistent < 0 || l.persistent > 2) return false;
+  if (l.grid_mult < 1 || l.grid_mult > 32) return false;
+  return true;
+}
+
+GridDev to_dev(const fc_grid& g) {
+  GridDev d;
+  d.data = g.data;
+  d.nx = g.nx;
+  d.ny = g.ny;
+  d.nz = g.nz;
+  int bx, by, bz;
+  bricks_of(g, bx, by, bz);
+  d.bx = bx;
+  d.by = by;
+  d.ox = g.origin[0];
+  d.oy = g.origin[1];
+  d.oz = g.origin[2];
+  d.inv_h = 1.f / g.h;
+  return d;
+}
+
+template <typename T>
+fc_status upload(T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return FC_OK;
+  FC_HIP(hipMalloc((void**)dst, v.size() * sizeof(T)));
+  FC_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FC_OK;
+}
+
+// --- a small JSON reader for the autotune cache -----------------------------
+struct JVal {
+  enum Kind { NUL, NUM, STR, ARR, OBJ, BOOL } kind = NUL;
+  double num = 0;
+  std::string str;
+  std::vector<JVal> arr;
+  std::vector<std::pair<std::string, JVal>> obj;
+};
+
+struct JParser {
+  const char* p;
+  const char* end;
+  void ws() {
+    while (p < end && std::isspace((unsigned char)*p)) ++p;
+  }
+  bool str(std::string& out) {
+    if (p >= end || *p != '"') return false;
+    ++p;
+    while (p < end && *p != '"') {
+      if (*p == '\\') {
+        ++p;
+        if (p >= end) return false;
+      }
+      out.push_back(*p++);
+    }
+    if (p >= end) return false;
+    ++p;
+    return true;
+  }
+  bool val(JVal& v, int depth) {
+    if (depth > 32) return false;
+    ws();
+    if (p >= end) return false;
+    if (*p == '{') {
+      ++p;
+      v.kind = JVal::OBJ;
+      ws();
+      if (p < end && *p == '}') {
+        ++p;
+        return true;
+      }
+      while (true) {
+        ws();
+        std::string k;
+        if (!str(k)) return false;
+        ws();
+        if (p >= end || *p != ':') return false;
+        ++p;
+        JVal c;
+        if (!val(c, depth + 1)) return false;
+        v.obj.emplace_back(k, c);
+        ws();
+        if (p < end && *p == ',') {
+          ++p;
+          continue;
+        }
+        if (p < end && *p == '}') {
+          ++p;
+          return true;
+        }
+        return false;
+      }
+    }
+    if (*p == '[') {
+      ++p;
+      v.kind = JVal::ARR;
+      ws();
+      if (p < end && *p == ']') {
+        ++p;
+        return true;
+      }
+      while (true) {
+        JVal c;
+        if (!val(c, depth + 1)) return false;
+        v.arr.push_back(c);
+        ws();
+        if (p < end && *p == ',') {
+          ++p;
+          continue;
+        }
+        if (p < end && *p == ']') {
+          ++p;
+          return true;
+        }
+        return false;
+      }
+    }
+    if (*p == '"') {
+      v.kind = JVal::STR;
+      return str(v.str);
+    }
+    if (end - p >= 4 && !std::strncmp(p, "true", 4)) {
+      v.kind = JVal::BOOL;
+      v.num = 1;
+      p += 4;
+      return true;
+    }
+    if (end - p >= 5 && !std::strncmp(p, "false", 5)) {
+      v.kind = JVal::BOOL;
+      p += 5;
+      return true;
+    }
+    if (end - p >= 4 && !std::strncmp(p, "null", 4)) {
+      p += 4;
+      return true;
+    }
+    char* q = nullptr;
+    std::string tmp(p, (size_t)std::min<ptrdiff_t>(end - p, 64));
+    const double d = std::strtod(tmp.c_str(), &q);
+    if (q == tmp.c_str()) return false;
+    v.kind = JVal::NUM;
+    v.num = d;
+    p += (q - tmp.c_str());
+    return true;
+  }
+};
+
+const JVal* jget(const JVal& o, const char* key) {
+  if (o.kind != JVal::OBJ) return nullptr;
+  for (auto& kv : o.obj)
+    if (kv.first == key) return &kv.second;
+  return nullptr;
+}
+
+}  // namespace
+
+struct fc_batch {
+  int n_env = 0, K = 0, dtype = 0, layout = 0;
+  float margin = 0.f;
+  std::vector<fc_grid> grids;
+  std::vector<fc_mesh> meshes;
+  std::vector<int> env_grid, env_mesh;
+  std::vector<float> dirs;
+  std::vector<long long> qoff;
+  long long Q = 0;
+  fc_launch launch{256, 1024, 0, 8};
+  int num_cus = 256;
+  std::string signature;
+  // forward tables
+  Item* d_items = nullptr;
+  int n_items = 0;
+  EnvInfo* d_envs = nullptr;
+  // backward tables
+  BwdItem* d_bitems = nullptr;
+  int n_bitems = 0;
+  BwdChunk* d_chunks = nullptr;
+  int n_chunks = 0;
+  int* d_env_list = nullptr;
+  int* d_env_tile_base = nullptr;
+  long long mesh_voff[FC_MAX_TYPES] = {0};
+  int mesh_tiles[FC_MAX_TYPES] = {0};
+  int mesh_chunk0[FC_MAX_TYPES] = {0};
+  int mesh_nchunks[FC_MAX_TYPES] = {0};
+  // workspace layout (bytes)
+  size_t off_keys = 0, off_workctr = 0, off_pose = 0, off_vert = 0, ws_bytes = 0;
+};
+
+namespace {
+
+void free_tables(fc_batch* b) {
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_envs) (void)hipFree(b->d_envs);
+  if (b->d_bitems) (void)hipFree(b->d_bitems);
+  if (b->d_chunks) (void)hipFree(b->d_chunks);
+  if (b->d_env_list) (void)hipFree(b->d_env_list);
+  if (b->d_env_tile_base) (void)hipFree(b->d_env_tile_base);
+  b->d_items = nullptr;
+  b->d_envs = nullptr;
+  b->d_bitems = nullptr;
+  b->d_chunks = nullptr;
+  b->d_env_list = nullptr;
+  b->d_env_tile_base = nullptr;
+}
+
+int gm_of(const fc_batch* b, int e) { return b->env_grid[e] | (b->env_mesh[e] << 8); }
+
+fc_status build_forward_tables(fc_batch* b) {
+  std::vector<Item> items;
+  std::vector<EnvInfo> envs(b->n_env);
+  const int tile = b->launch.tile;
+  for (int e = 0; e < b->n_env; ++e) {
+    const int n = b->meshes[b->env_mesh[e]].n_verts;
+    const int ni = n > 0 ? ceil_div(n, tile) : 1;
+    envs[e].qoff = b->qoff[e];
+    envs[e].n_items = ni;
+    envs[e].gm = gm_of(b, e);
+    for (int t = 0; t < ni; ++t) {
+      Item it;
+      it.env = e;
+      it.vstart = t * tile;
+      it.vcount = std::min(tile, n - t * tile);
+      if (it.vcount < 0) it.vcount = 0;
+      it.gm = gm_of(b, e);
+      items.push_back(it);
+    }
+  }
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_envs) (void)hipFree(b->d_envs);
+  b->d_items = nullptr;
+  b->d_envs = nullptr;
+  b->n_items = (int)items.size();
+  fc_status s = upload(&b->d_items, items);
+  if (s != FC_OK) return s;
+  return upload(&b->d_envs, envs);
+}
+
+fc_status build_backward_tables(fc_batch* b) {
+  const int nm = (int)b->meshes.size();
+  std::vector<int> env_list;
+  std::vector<BwdChunk> chunks;
+  std::vector<BwdItem> items;
+  std::vector<int> env_tile_base(b->n_env);
+  // tiles per mesh (>= 1 so that an empty mesh still produces its poses' partials)
+  for (int m = 0; m < nm; ++m) {
+    const int n = b->meshes[m].n_verts;
+    b->mesh_tiles[m] = n > 0 ? ceil_div(n, kBwdTile) : 1;
+  }
+  // pose partial rows, env order
+  int rows = 0;
+  for (int e = 0; e < b->n_env; ++e) {
+    env_tile_base[e] = rows;
+    rows += b->mesh_tiles[b->env_mesh[e]];
+  }
+  // chunks: grouped by mesh, then grid, then env order
+  long long vpart = 0;
+  long long voff = 0;
+  for (int m = 0; m < nm; ++m) {
+    b->mesh_voff[m] = voff;
+    voff += 3LL * b->meshes[m].n_verts;
+    b->mesh_chunk0[m] = (int)chunks.size();
+    for (int g = 0; g < (int)b->grids.size(); ++g) {
+      std::vector<int> grp;
+      for (int e = 0; e < b->n_env; ++e)
+        if (b->env_mesh[e] == m && b->env_grid[e] == g) grp.push_back(e);
+      for (size_t i = 0; i < grp.size(); i += kBwdChunk) {
+        BwdChunk c;
+        c.first = (int)env_list.size();
+        c.len = (int)std::min<size_t>(kBwdChunk, grp.size() - i);
+        c.n_tiles = b->mesh_tiles[m];
+        c.mesh = m;
+        c.vpart = vpart;
+        vpart += 3LL * b->meshes[m].n_verts;
+        for (int k = 0; k < c.len; ++k) env_list.push_back(grp[i + k]);
+        const int cid = (int)chunks.size();
+        chunks.push_back(c);
+        for (int t = 0; t < b->mesh_tiles[m]; ++t) {
+          BwdItem it;
+          it.vstart = t * kBwdTile;
+          it.vcount = std::max(0, std::min(kBwdTile, b->meshes[m].n_verts - t * kBwdTile));
+          it.gm = g | (m << 8);
+          it.chunk = cid;
+          it.tile = 0;
+          it.tile_in_mesh = t;
+          it.pad0 = it.pad1 = 0;
+          items.push_back(it);
+        }
+      }
+    }
+    b->mesh_nchunks[m] = (int)chunks.size() - b->mesh_chunk0[m];
+  }
+  b->n_bitems = (int)items.size();
+  b->n_chunks = (int)chunks.size();
+  fc_status s;
+  if ((s = upload(&b->d_bitems, items)) != FC_OK) return s;
+  if ((s = upload(&b->d_chunks, chunks)) != FC_OK) return s;
+  if ((s = upload(&b->d_env_list, env_list)) != FC_OK) return s;
+  if ((s = upload(&b->d_env_tile_base, env_tile_base)) != FC_OK) return s;
+  // workspace layout
+  size_t off = 0;
+  b->off_keys = off;
+  off = align256(off + (size_t)b->n_env * b->K * 8);
+  b->off_workctr = off;
+  off = align256(off + 2 * 4);
+  b->off_pose = off;
+  off = align256(off + (size_t)rows * 8 * sizeof(float2));
+  b->off_vert = off;
+  off = align256(off + (size_t)vpart * sizeof(float2));
+  b->ws_bytes = off;
+  return FC_OK;
+}
+
+std::string make_signature(const fc_batch* b) {
+  std::string s = "v1;dt=" + std::to_string(b->dtype) + ";lay=" + std::to_string(b->layout) +
+                  ";K=" + std::to_string(b->K) + ";env=" + std::to_string(b->n_env) + ";grids=";
+  for (auto& g : b->grids) s += std::to_string(g.nx) + "x" + std::to_string(g.ny) + "x" + std::to_string(g.nz) + ",";
+  s += ";meshes=";
+  for (auto& m : b->meshes) s += std::to_string(m.n_verts) + ",";
+  return s;
+}
+
+fc_status check_ws(const fc_batch* b, void* ws, size_t ws_bytes) {
+  if (!ws) return FC_ERR_WORKSPACE;
+  if (ws_bytes < b->ws_bytes) return FC_ERR_WORKSPACE;
+  if (((uintptr_t)ws) & 255u) return FC_ERR_WORKSPACE;
+  return FC_OK;
+}
+
+void fill_common(const fc_batch* b, GridDev* grids, MeshDev* meshes) {
+  for (size_t i = 0; i < b->grids.size(); ++i) grids[i] = to_dev(b->grids[i]);
+  for (size_t i = 0; i < b->meshes.size(); ++i) {
+    meshes[i].x = b->meshes[i].x;
+    meshes[i].y = b->meshes[i].y;
+    meshes[i].z = b->meshes[i].z;
+    meshes[i].n = b->meshes[i].n_verts;
+    meshes[i].pad = 0;
+  }
+}
+
+FwdArgs make_fwd(const fc_batch* b, const float* pose, const fc_candidates* cand, const fc_contacts* out, void* ws) {
+  FwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  fill_common(b, a.grids, a.meshes);
+  for (int i = 0; i < 3 * b->K; ++i) a.dirs[i] = b->dirs[i];
+  a.items = b->d_items;
+  a.envs = b->d_envs;
+  a.pose = pose;
+  a.n_items = b->n_items;
+  a.n_env = b->n_env;
+  a.K = b->K;
+  a.margin = b->margin;
+  a.Q = b->Q;
+  if (cand) {
+    a.c_phi = cand->phi;
+    a.c_nrm = cand->normal;
+    a.c_bin = cand->bin;
+  }
+  if (out) {
+    a.o_vidx = out->vidx;
+    a.o_depth = out->depth;
+    a.o_point = out->point;
+    a.o_nrm = out->normal;
+    a.o_count = out->count;
+  }
+  char* w = static_cast<char*>(ws);
+  a.keys = reinterpret_cast<unsigned long long*>(w + b->off_keys);
+  a.work_ctr = reinterpret_cast<unsigned*>(w + b->off_workctr);
+  return a;
+}
+
+int forward_grid(const fc_batch* b) {
+  if (b->launch.persistent == 0) return b->n_items;
+  const long long g = (long long)b->num_cus * b->launch.grid_mult;
+  return (int)std::min<long long>(g, b->n_items);
+}
+
+bool contacts_ok(const fc_contacts* o) {
+  return o->vidx && o->depth && o->point && o->normal && o->count;
+}
+
+fc_status enqueue_forward(const fc_batch* b, const float* pose, const fc_candidates* cand, const fc_contacts* out,
+                          void* ws, hipStream_t s, bool from_cand) {
+  const FwdArgs a = make_fwd(b, pose, cand, out, ws);
+  const int vpt = b->launch.tile / b->launch.block;
+  FC_HIP(launch_forward(a, b->dtype, b->layout, b->launch.block, vpt, b->launch.persistent, forward_grid(b),
+                        from_cand, s));
+  return FC_OK;
+}
+
+fc_status enqueue_backward(const fc_batch* b, const float* pose, float k, const float* upstream, const fc_grads* out,
+                           void* ws, hipStream_t s) {
+  BwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  fill_common(b, a.grids, a.meshes);
+  for (int m = 0; m < FC_MAX_TYPES; ++m) {
+    a.mesh_voff[m] = b->mesh_voff[m];
+    a.mesh_tiles[m] = b->mesh_tiles[m];
+    a.mesh_chunk0[m] = b->mesh_chunk0[m];
+    a.mesh_nchunks[m] = b->mesh_nchunks[m];
+  }
+  a.n_meshes = (int)b->meshes.size();
+  a.items = b->d_bitems;
+  a.chunks = b->d_chunks;
+  a.env_list = b->d_env_list;
+  a.env_tile_base = b->d_env_tile_base;
+  a.envs = b->d_envs;
+  a.pose = pose;
+  a.upstream = upstream;
+  a.n_items = b->n_bitems;
+  a.n_env = b->n_env;
+  a.k = k;
+  a.per_env = out->verts_per_env ? 1 : 0;
+  a.Q = b->Q;
+  a.loss = out->loss;
+  a.d_pose = out->d_pose;
+  a.d_verts = out->d_verts;
+  char* w = static_cast<char*>(ws);
+  a.pose_part = reinterpret_cast<float2*>(w + b->off_pose);
+  a.vert_part = reinterpret_cast<float2*>(w + b->off_vert);
+  FC_HIP(launch_backward(a, b->dtype, b->layout, s));
+  return FC_OK;
+}
+
+fc_status validate_backward(const fc_batch* b, const float* pose, float k, const fc_grads* out, void* ws,
+                            size_t ws_bytes) {
+  if (!b || !pose || !out) return FC_ERR_NULL;
+  if (!out->loss && !out->d_pose && !out->d_verts) return FC_ERR_NULL;
+  if (!(k > 0.f) || !finitef(k)) return FC_ERR_RANGE;
+  return check_ws(b, ws, ws_bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fc_version(void) { return "factory_sdf 1.0 (gfx950)"; }
+
+const char* fc_status_str(fc_status s) {
+  switch (s) {
+    case FC_OK: return "ok";
+    case FC_ERR_NULL: return "required pointer is NULL";
+    case FC_ERR_SHAPE: return "size or count out of range";
+    case FC_ERR_DTYPE: return "unknown or mixed dtype / layout";
+    case FC_ERR_RANGE: return "numeric parameter out of range";
+    case FC_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case FC_ERR_HIP: return "HIP runtime error";
+    case FC_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+int32_t fc_last_hip_error(void) { return g_last_hip; }
+
+fc_status fc_batch_create(const fc_batch_desc* desc, fc_batch** out) {
+  if (!out) return FC_ERR_NULL;
+  *out = nullptr;
+  fc_status s = validate_desc(desc);
+  if (s != FC_OK) return s;
+  fc_batch* b = new fc_batch();
+  b->n_env = desc->n_env;
+  b->K = desc->n_bins;
+  b->dtype = desc->grids[0].dtype;
+  b->layout = desc->grids[0].layout;
+  b->margin = desc->margin;
+  b->grids.assign(desc->grids, desc->grids + desc->n_grids);
+  b->meshes.assign(desc->meshes, desc->meshes + desc->n_meshes);
+  b->env_grid.resize(b->n_env);
+  b->env_mesh.resize(b->n_env);
+  b->qoff.resize(b->n_env);
+  long long q = 0;
+  for (int e = 0; e < b->n_env; ++e) {
+    b->env_grid[e] = desc->env_grid ? desc->env_grid[e] : 0;
+    b->env_mesh[e] = desc->env_mesh ? desc->env_mesh[e] : 0;
+    b->qoff[e] = q;
+    q += b->meshes[b->env_mesh[e]].n_verts;
+  }
+  b->Q = q;
+  b->dirs.assign(desc->bin_dirs, desc->bin_dirs + 3 * b->K);
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he == hipSuccess) he = hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (he != hipSuccess) {
+    delete b;
+    return hip_fail(he);
+  }
+  b->signature = make_signature(b);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(b->signature);
+    if (it != g_tune.end() && launch_valid(it->second)) b->launch = it->second;
+  }
+  s = build_forward_tables(b);
+  if (s == FC_OK) s = build_backward_tables(b);
+  if (s != FC_OK) {
+    free_tables(b);
+    delete b;
+    return s;
+  }
+  *out = b;
+  return FC_OK;
+}
+
+void fc_batch_destroy(fc_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  free_tables(b);
+  delete b;
+}
+
+int64_t fc_batch_queries(const fc_batch* b) { return b ? b->Q : -1; }
+
+fc_status fc_batch_set_launch(fc_batch* b, const fc_launch* l) {
+  if (!b || !l) return FC_ERR_NULL;
+  if (!launch_valid(*l)) return FC_ERR_RANGE;
+  const bool retile = l->tile != b->launch.tile;
+  b->launch = *l;
+  if (retile) {
+    FC_HIP(hipDeviceSynchronize());
+    return build_forward_tables(b);
+  }
+  return FC_OK;
+}
+
+fc_status fc_batch_get_launch(const fc_batch* b, fc_launch* out) {
+  if (!b || !out) return FC_ERR_NULL;
+  *out = b->launch;
+  return FC_OK;
+}
+
+int32_t fc_batch_signature(const fc_batch* b, char* buf, int32_t cap) {
+  if (!b) return -1;
+  if (buf && cap > 0) {
+    const size_t n = std::min<size_t>((size_t)cap - 1, b->signature.size());
+    std::memcpy(buf, b->signature.data(), n);
+    buf[n] = '\0';
+  }
+  return (int32_t)b->signature.size();
+}
+
+size_t fc_workspace_bytes(const fc_batch* b) { return b ? b->ws_bytes : 0; }
+
+fc_status fc_workspace_init(const fc_batch* b, void* ws, size_t ws_bytes, void* stream) {
+  if (!b) return FC_ERR_NULL;
+  fc_status s = check_ws(b, ws, ws_bytes);
+  if (s != FC_OK) return s;
+  FC_HIP(launch_zero(ws, b->ws_bytes, (hipStream_t)stream));
+  return FC_OK;
+}
+
+fc_status fc_sdf_query(const fc_batch* b, const float* pose, const fc_candidates* cand, const fc_contacts* fused_out,
+                       void* ws, size_t ws_bytes, void* stream) {
+  if (!b || !pose) return FC_ERR_NULL;
+  if (!cand && !fused_out) return FC_ERR_NULL;
+  if (cand && (!cand->phi || !cand->normal || !cand->bin)) return FC_ERR_NULL;
+  if (fused_out && !contacts_ok(fused_out)) return FC_ERR_NULL;
+  fc_status s = check_ws(b, ws, ws_bytes);
+  if (s != FC_OK) return s;
+  return enqueue_forward(b, pose, cand, fused_out, ws, (hipStream_t)stream, false);
+}
+
+fc_status fc_contact_reduce(const fc_batch* b, const float* pose, const fc_candidates* cand, const fc_contacts* out,
+                            void* ws, size_t ws_bytes, void* stream) {
+  if (!b || !pose || !cand || !out) return FC_ERR_NULL;
+  if (!cand->phi || !cand->normal || !cand->bin || !contacts_ok(out)) return FC_ERR_NULL;
+  fc_status s = check_ws(b, ws, ws_bytes);
+  if (s != FC_OK) return s;
+  return enqueue_forward(b, pose, cand, out, ws, (hipStream_t)stream, true);
+}
+
+fc_status fc_sdf_query_backward(const fc_batch* b, const float* pose, float k, const float* upstream,
+                                const fc_grads* out, void* ws, size_t ws_bytes, void* stream) {
+  fc_status s = validate_backward(b, pose, k, out, ws, ws_bytes);
+  if (s != FC_OK) return s;
+  return enqueue_backward(b, pose, k, upstream, out, ws, (hipStream_t)stream);
+}
+
+struct fc_graph {
+  hipGraphExec_t exec = nullptr;
+};
+
+fc_status fc_graph_create(const fc_batch* b, const float* pose, const fc_contacts* fused_out, float k,
+                          const float* upstream, const fc_grads* grads, void* ws, size_t ws_bytes, fc_graph** out) {
+  if (!out) return FC_ERR_NULL;
+  *out = nullptr;
+  if (!b || !pose) return FC_ERR_NULL;
+  if (!fused_out && !grads) return FC_ERR_NULL;
+  if (fused_out && !contacts_ok(fused_out)) return FC_ERR_NULL;
+  fc_status s = check_ws(b, ws, ws_bytes);
+  if (s != FC_OK) return s;
+  if (grads) {
+    s = validate_backward(b, pose, k, grads, ws, ws_bytes);
+    if (s != FC_OK) return s;
+  }
+  hipStream_t cs = nullptr;
+  FC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return hip_fail(he);
+  }
+  if (fused_out) s = enqueue_forward(b, pose, nullptr, fused_out, ws, cs, false);
+  if (s == FC_OK && grads) s = enqueue_backward(b, pose, k, upstream, grads, ws, cs);
+  hipGraph_t graph = nullptr;
+  he = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (s != FC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (he != hipSuccess) return hip_fail(he);
+  hipGraphExec_t exec = nullptr;
+  he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (he != hipSuccess) return hip_fail(he);
+  fc_graph* g = new fc_graph();
+  g->exec = exec;
+  *out = g;
+  return FC_OK;
+}
+
+fc_status fc_graph_launch(fc_graph* g, void* stream) {
+  if (!g || !g->exec) return FC_ERR_NULL;
+  FC_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return FC_OK;
+}
+
+void fc_graph_destroy(fc_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  delete g;
+}
+
+size_t fc_grid_brick_bytes(const fc_grid* src) {
+  if (!src) return 0;
+  fc_grid g = *src;
+  g.layout = FC_LAYOUT_BRICK;
+  if (!g.data) g.data = (const void*)1;  // size query only
+  if (check_grid(g) != FC_OK) return 0;
+  int bx, by, bz;
+  bricks_of(g, bx, by, bz);
+  return (size_t)bx * by * bz * kBrickNodes * kBrickNodes * kBrickNodes * elem_size(g.dtype);
+}
+
+fc_status fc_grid_to_bricks(const fc_grid* src, void* dst_data, size_t dst_bytes, fc_grid* dst, void* stream) {
+  if (!src || !dst_data || !dst) return FC_ERR_NULL;
+  fc_status s = check_grid(*src);
+  if (s != FC_OK) return s;
+  if (src->layout != FC_LAYOUT_LINEAR) return FC_ERR_DTYPE;
+  const size_t need = fc_grid_brick_bytes(src);
+  if (need == 0) return FC_ERR_SHAPE;
+  if (dst_bytes < need) return FC_ERR_WORKSPACE;
+  int bx, by, bz;
+  bricks_of(*src, bx, by, bz);
+  FC_HIP(launch_to_bricks(src->data, dst_data, elem_size(src->dtype), src->nx, src->ny, src->nz, bx, by, bz,
+                          (hipStream_t)stream));
+  *dst = *src;
+  dst->data = dst_data;
+  dst->layout = FC_LAYOUT_BRICK;
+  return FC_OK;
+}
+
+int32_t fc_autotune_load(const char* path) {
+  if (!path) return -1;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return -1;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+  std::fclose(f);
+  JParser p{text.data(), text.data() + text.size()};
+  JVal root;
+  if (!p.val(root, 0)) return -1;
+  const JVal* entries = jget(root, "entries");
+  if (!entries || entries->kind != JVal::ARR) return -1;
+  int loaded = 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const JVal& e : entries->arr) {
+    const JVal* key = jget(e, "key");
+    const JVal* bl = jget(e, "block");
+    const JVal* ti = jget(e, "tile");
+    const JVal* pe = jget(e, "persistent");
+    const JVal* gm = jget(e, "grid_mult");
+    if (!key || key->kind != JVal::STR || !bl || !ti || !pe || !gm) continue;
+    fc_launch l{(int32_t)bl->num, (int32_t)ti->num, (int32_t)pe->num, (int32_t)gm->num};
+    if (!launch_valid(l)) continue;
+    g_tune[key->str] = l;
+    ++loaded;
+  }
+  return loaded;
+}
+
+}  // extern "C"

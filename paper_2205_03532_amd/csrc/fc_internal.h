@@ -1,0 +1,134 @@
+// Internal declarations shared by the host ABI (fc_api.cpp) and the HIP
+// kernels (fc_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fc.h"
+
+namespace fcimpl {
+
+// Backward work decomposition.  These fix the order of every floating-point
+// sum in the adjoint, so they are constants, never tuned: the gradients are
+// bit-identical for every launch shape of the forward kernels.
+constexpr int kBwdTile = 512;   // vertices per backward item (pose partial sums)
+constexpr int kBwdBlock = 256;  // threads per backward workgroup (2 vertices each)
+constexpr int kBwdChunk = 32;   // environments per backward item (vertex partial sums)
+
+// Brick layout: 4x4x4 nodes per brick covering 3x3x3 cells.
+constexpr int kBrickCells = 3;
+constexpr int kBrickNodes = 4;
+
+struct GridDev {
+  const void* data;
+  int nx, ny, nz;
+  int bx, by;  // bricks along x and y (brick layout)
+  float ox, oy, oz;
+  float inv_h;
+};
+
+struct MeshDev {
+  const float* x;
+  const float* y;
+  const float* z;
+  int n;
+  int pad;
+};
+
+struct Item {  // one forward work item: a tile of one environment's vertices
+  int env;
+  int vstart;
+  int vcount;
+  int gm;  // grid index | mesh index << 8
+};
+
+struct EnvInfo {
+  long long qoff;  // first query index of the env
+  int n_items;     // forward items of the env (>= 1)
+  int gm;
+};
+
+struct FwdArgs {
+  GridDev grids[FC_MAX_TYPES];
+  MeshDev meshes[FC_MAX_TYPES];
+  float dirs[3 * FC_MAX_BINS];  // [3][K]
+  const Item* items;
+  const EnvInfo* envs;
+  const float* pose;  // [7][n_env]
+  int n_items;
+  int n_env;
+  int K;
+  float margin;
+  long long Q;
+  // candidates (may be null)
+  float* c_phi;
+  float* c_nrm;
+  int16_t* c_bin;
+  // reduced contacts (may be null)
+  int* o_vidx;
+  float* o_depth;
+  float* o_point;
+  float* o_nrm;
+  int* o_count;
+  // workspace (zero between calls)
+  unsigned long long* keys;  // [n_env][K] per-bin maxima, taken and reset by the payload kernel
+  unsigned* work_ctr;        // [2] persistent work counter, reset by the payload kernel
+};
+
+struct BwdItem {
+  int vstart;
+  int vcount;
+  int gm;
+  int chunk;  // chunk id: envs env_list[chunk_first[chunk] .. + chunk_len[chunk])
+  int tile;   // global tile id
+  int tile_in_mesh;
+  int pad0, pad1;
+};
+
+struct BwdChunk {
+  int first;      // into env_list
+  int len;        // envs in this chunk (<= kBwdChunk)
+  int n_tiles;    // tiles of the chunk's mesh
+  int mesh;
+  long long vpart;  // offset (in float2) of this chunk's vertex partials [3][n_v]
+};
+
+struct BwdArgs {
+  GridDev grids[FC_MAX_TYPES];
+  MeshDev meshes[FC_MAX_TYPES];
+  long long mesh_voff[FC_MAX_TYPES];  // shared-mode d_verts offset (floats) of mesh m
+  int mesh_tiles[FC_MAX_TYPES];       // backward tiles of mesh m (>= 1)
+  int mesh_chunk0[FC_MAX_TYPES];      // first chunk of mesh m (chunks of a mesh are contiguous)
+  int mesh_nchunks[FC_MAX_TYPES];     // chunks of mesh m
+  int n_meshes;
+  const BwdItem* items;
+  const BwdChunk* chunks;
+  const int* env_list;
+  const int* env_tile_base;  // [n_env] first pose-partial row of the env
+  const EnvInfo* envs;
+  const float* pose;
+  const float* upstream;
+  int n_items;
+  int n_env;
+  float k;
+  int per_env;
+  long long Q;
+  float* loss;
+  float* d_pose;
+  float* d_verts;
+  // workspace: partial sums, fully overwritten by every call
+  float2* pose_part;  // [rows][8]: 7 used
+  float2* vert_part;  // per chunk [3][n_v]
+};
+
+// launch wrappers (fc_kernels.hip)
+hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent,
+                          int grid, bool from_cand, hipStream_t s);
+hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_to_bricks(const void* src, void* dst, int elem, int nx, int ny, int nz, int bx, int by, int bz,
+                            hipStream_t s);
+bool forward_shape_supported(int block, int vpt);
+
+}  // namespace fcimpl

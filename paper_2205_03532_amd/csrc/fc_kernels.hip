@@ -1,0 +1,767 @@
+// HIP kernels for gfx950 (CDNA4): vertex-vs-SDF queries, contact reduction
+// and the penetration-penalty adjoint.
+//
+// What is computed (Narang et al., Factory, RSS 2022):
+//   Section III-A -- the SDF is a grid read with trilinear filtering; value
+//   and gradient give a contact's distance and normal.
+//   Section III-C, Algorithm 1 -- Generate candidate contacts for a batch of
+//   the mesh's features, then FindDeepest / BinReduce: here the deepest
+//   candidate per fixed normal-direction bin, lowest vertex index on ties.
+//   The reduction runs on chip (LDS) inside the generating kernel, as the
+//   paper does in shared memory so that candidates never reach global memory.
+//
+// Numerics: this file is compiled with -ffp-contract=off; every fused
+// multiply-add is an explicit fmaf.  All code paths that evaluate a query
+// (candidate pass, fused pass, winner recompute, adjoint) call the same
+// inline functions, so they produce the same bits.
+//
+// The path is a gather-bound stencil (8 corner loads per query and about 100
+// flops), so there is no MFMA here: the design work is in the gather
+// (coalesced SoA vertex reads, corner pairs loaded as one 8-byte access,
+// optional brick layout keeping a cell's corners in one 128-byte line) and in
+// keeping the reduction on chip (wave ballot / butterfly max, LDS atomics,
+// one global 64-bit atomicMax per bin per work item).
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "fc_internal.h"
+
+namespace fcimpl {
+namespace {
+
+constexpr int kF32 = FC_F32, kF16 = FC_F16, kBF16 = FC_BF16;
+
+// ---------------------------------------------------------------------------
+// rigid transform (quaternion x,y,z,w -> R = I + 2w[v]x + 2[v]x^2, no renormalisation)
+// ---------------------------------------------------------------------------
+struct Rigid {
+  float r00, r01, r02, r10, r11, r12, r20, r21, r22, tx, ty, tz;
+};
+
+__device__ __forceinline__ Rigid load_pose(const float* __restrict__ pose, int n_env, int e) {
+  const float qx = pose[e], qy = pose[n_env + e], qz = pose[2 * n_env + e], qw = pose[3 * n_env + e];
+  const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+  const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
+  const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+  Rigid r;
+  r.r00 = 1.f - 2.f * (yy + zz);
+  r.r01 = 2.f * (xy - wz);
+  r.r02 = 2.f * (xz + wy);
+  r.r10 = 2.f * (xy + wz);
+  r.r11 = 1.f - 2.f * (xx + zz);
+  r.r12 = 2.f * (yz - wx);
+  r.r20 = 2.f * (xz - wy);
+  r.r21 = 2.f * (yz + wx);
+  r.r22 = 1.f - 2.f * (xx + yy);
+  r.tx = pose[4 * n_env + e];
+  r.ty = pose[5 * n_env + e];
+  r.tz = pose[6 * n_env + e];
+  return r;
+}
+
+__device__ __forceinline__ void transform(const Rigid& P, float x, float y, float z, float& ox, float& oy,
+                                          float& oz) {
+  ox = fmaf(P.r00, x, fmaf(P.r01, y, fmaf(P.r02, z, P.tx)));
+  oy = fmaf(P.r10, x, fmaf(P.r11, y, fmaf(P.r12, z, P.ty)));
+  oz = fmaf(P.r20, x, fmaf(P.r21, y, fmaf(P.r22, z, P.tz)));
+}
+
+// ---------------------------------------------------------------------------
+// grid access
+// ---------------------------------------------------------------------------
+struct Cell {
+  int ix, iy, iz;
+  float tx, ty, tz;
+  bool inside;
+};
+
+// Grid coordinate u = (x - origin)/h; inside iff 0 <= u <= n-1 on every axis;
+// cell = min(floor(u), n-2); t = u - cell.
+__device__ __forceinline__ Cell locate(const GridDev& g, float x, float y, float z) {
+  float ux = (x - g.ox) * g.inv_h;
+  float uy = (y - g.oy) * g.inv_h;
+  float uz = (z - g.oz) * g.inv_h;
+  Cell c;
+  c.inside = (ux >= 0.f) & (ux <= (float)(g.nx - 1)) & (uy >= 0.f) & (uy <= (float)(g.ny - 1)) & (uz >= 0.f) &
+             (uz <= (float)(g.nz - 1));
+  if (!c.inside) ux = uy = uz = 0.f;  // also clears NaN: the gather stays in bounds
+  c.ix = min((int)floorf(ux), g.nx - 2);
+  c.iy = min((int)floorf(uy), g.ny - 2);
+  c.iz = min((int)floorf(uz), g.nz - 2);
+  c.tx = ux - (float)c.ix;
+  c.ty = uy - (float)c.iy;
+  c.tz = uz - (float)c.iz;
+  return c;
+}
+
+// (v[i], v[i+1]) as one unaligned 8-byte (FP32) or 4-byte (FP16/BF16) load
+template <int DT>
+__device__ __forceinline__ float2 ld_pair(const void* __restrict__ base, int i);
+
+template <>
+__device__ __forceinline__ float2 ld_pair<kF32>(const void* __restrict__ base, int i) {
+  float2 r;
+  __builtin_memcpy(&r, static_cast<const float*>(base) + i, 8);
+  return r;
+}
+template <>
+__device__ __forceinline__ float2 ld_pair<kF16>(const void* __restrict__ base, int i) {
+  unsigned u;
+  __builtin_memcpy(&u, static_cast<const uint16_t*>(base) + i, 4);
+  return make_float2(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))),
+                     __half2float(__ushort_as_half((unsigned short)(u >> 16))));
+}
+template <>
+__device__ __forceinline__ float2 ld_pair<kBF16>(const void* __restrict__ base, int i) {
+  unsigned u;
+  __builtin_memcpy(&u, static_cast<const uint16_t*>(base) + i, 4);
+  return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+}
+
+// Corner order: c[a + 2b + 4c] = value at node (ix+a, iy+b, iz+c).
+template <int DT, int LAYOUT>
+__device__ __forceinline__ void gather(const GridDev& g, const Cell& cl, float c[8]) {
+  int i0, sy, sz;
+  if (LAYOUT == FC_LAYOUT_LINEAR) {
+    sy = g.nx;
+    sz = g.nx * g.ny;
+    i0 = (cl.iz * g.ny + cl.iy) * g.nx + cl.ix;
+  } else {
+    const int bxi = cl.ix / kBrickCells, byi = cl.iy / kBrickCells, bzi = cl.iz / kBrickCells;
+    const int lx = cl.ix - kBrickCells * bxi, ly = cl.iy - kBrickCells * byi, lz = cl.iz - kBrickCells * bzi;
+    sy = kBrickNodes;
+    sz = kBrickNodes * kBrickNodes;
+    i0 = ((bzi * g.by + byi) * g.bx + bxi) * (kBrickNodes * kBrickNodes * kBrickNodes) + (lz * sz + ly * sy + lx);
+  }
+  const float2 p00 = ld_pair<DT>(g.data, i0);
+  const float2 p10 = ld_pair<DT>(g.data, i0 + sy);
+  const float2 p01 = ld_pair<DT>(g.data, i0 + sz);
+  const float2 p11 = ld_pair<DT>(g.data, i0 + sz + sy);
+  c[0] = p00.x; c[1] = p00.y;
+  c[2] = p10.x; c[3] = p10.y;
+  c[4] = p01.x; c[5] = p01.y;
+  c[6] = p11.x; c[7] = p11.y;
+}
+
+// Trilinear value and its exact gradient in grid units (multiply by 1/h for
+// metres): phi = sum W_a(tx) W_b(ty) W_c(tz) C_abc, evaluated as nested lerps.
+__device__ __forceinline__ void trilinear(const float c[8], float tx, float ty, float tz, float& phi, float& gx,
+                                          float& gy, float& gz) {
+  const float dx00 = c[1] - c[0], dx10 = c[3] - c[2], dx01 = c[5] - c[4], dx11 = c[7] - c[6];
+  const float a00 = fmaf(tx, dx00, c[0]);
+  const float a10 = fmaf(tx, dx10, c[2]);
+  const float a01 = fmaf(tx, dx01, c[4]);
+  const float a11 = fmaf(tx, dx11, c[6]);
+  const float dy0 = a10 - a00, dy1 = a11 - a01;
+  const float b0 = fmaf(ty, dy0, a00);
+  const float b1 = fmaf(ty, dy1, a01);
+  const float dz = b1 - b0;
+  phi = fmaf(tz, dz, b0);
+  gz = dz;
+  gy = fmaf(tz, dy1 - dy0, dy0);
+  const float e0 = fmaf(ty, dx10 - dx00, dx00);
+  const float e1 = fmaf(ty, dx11 - dx01, dx01);
+  gx = fmaf(tz, e1 - e0, e0);
+}
+
+template <int DT, int LAYOUT>
+__device__ __forceinline__ void sample(const GridDev& g, float x, float y, float z, float& phi, float& gx, float& gy,
+                                       float& gz, bool& inside) {
+  const Cell cl = locate(g, x, y, z);
+  float c[8];
+  gather<DT, LAYOUT>(g, cl, c);
+  trilinear(c, cl.tx, cl.ty, cl.tz, phi, gx, gy, gz);
+  inside = cl.inside;
+}
+
+__device__ __forceinline__ void normalize(float gx, float gy, float gz, float& nx, float& ny, float& nz) {
+  const float l2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+  if (l2 > 0.f) {
+    const float r = rsqrtf(l2);
+    nx = gx * r;
+    ny = gy * r;
+    nz = gz * r;
+  } else {
+    nx = ny = nz = 0.f;
+  }
+}
+
+// lowest k maximising n . d_k
+__device__ __forceinline__ int argmax_bin(const float* __restrict__ dirs, int K, float nx, float ny, float nz) {
+  float best = fmaf(nz, dirs[2 * K], fmaf(ny, dirs[K], nx * dirs[0]));
+  int bin = 0;
+  for (int k = 1; k < K; ++k) {
+    const float d = fmaf(nz, dirs[2 * K + k], fmaf(ny, dirs[K + k], nx * dirs[k]));
+    if (d > best) {
+      best = d;
+      bin = k;
+    }
+  }
+  return bin;
+}
+
+// ---------------------------------------------------------------------------
+// reduction keys: (sortable depth << 32) | (0xFFFFFFFF - vidx); max = deepest,
+// then lowest index.  -0.0 is folded to +0.0; key 0 means "empty".
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long make_key(float depth, unsigned vidx) {
+  if (depth == 0.f) depth = 0.f;
+  unsigned u = __float_as_uint(depth);
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - vidx);
+}
+
+__device__ __forceinline__ float key_depth(unsigned long long key) {
+  unsigned u = (unsigned)(key >> 32);
+  u = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+  return __uint_as_float(u);
+}
+
+__device__ __forceinline__ unsigned key_vidx(unsigned long long key) { return 0xFFFFFFFFu - (unsigned)key; }
+
+// Per-bin max over the candidate lanes of a wavefront: one iteration per
+// distinct bin present (ballot picks the bin, a butterfly of shuffles takes
+// the 64-bit max), then one LDS atomicMax by the bin's leader lane.
+__device__ __forceinline__ void wave_bin_max(bool cand, int bin, unsigned long long key,
+                                             unsigned long long* s_keys) {
+  unsigned long long active = __ballot(cand);
+  const int lane = __lane_id();
+  while (active) {
+    const int leader = __ffsll((long long)active) - 1;
+    const int lb = __shfl(bin, leader);
+    const bool mine = cand && (bin == lb);
+    const unsigned long long m = __ballot(mine);
+    unsigned long long v = mine ? key : 0ull;
+    if (__popcll(m) > 1) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+      }
+    }
+    if (lane == leader) atomicMax(&s_keys[lb], v);
+    active &= ~m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward: one work item = up to BLOCK*VPT vertices of one environment
+// ---------------------------------------------------------------------------
+template <int DT, int LAYOUT, int BLOCK, int VPT>
+__device__ __forceinline__ void query_item(const FwdArgs& A, const Item& it, unsigned long long* s_keys, bool fused) {
+  const GridDev& g = A.grids[it.gm & 0xff];
+  const MeshDev& m = A.meshes[it.gm >> 8];
+  const Rigid P = load_pose(A.pose, A.n_env, it.env);
+  const int tid = threadIdx.x;
+  const int vend = it.vstart + it.vcount;
+
+  float px[VPT], py[VPT], pz[VPT];
+  bool ok[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int v = it.vstart + j * BLOCK + tid;
+    ok[j] = v < vend;
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (ok[j]) {
+      x = m.x[v];
+      y = m.y[v];
+      z = m.z[v];
+    }
+    transform(P, x, y, z, px[j], py[j], pz[j]);
+  }
+  Cell cl[VPT];
+  float c[VPT][8];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) cl[j] = locate(g, px[j], py[j], pz[j]);
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) gather<DT, LAYOUT>(g, cl[j], c[j]);
+
+  const bool want_cand = A.c_phi != nullptr;
+  const long long qoff = want_cand ? A.envs[it.env].qoff : 0;
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    float phi, gx, gy, gz;
+    trilinear(c[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
+    const bool inside = ok[j] & cl[j].inside;
+    const bool cand = inside & (phi < A.margin);
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    int bin = -1;
+    if (cand | (want_cand & inside)) normalize(gx, gy, gz, nx, ny, nz);
+    if (cand) bin = argmax_bin(A.dirs, A.K, nx, ny, nz);
+    const int v = it.vstart + j * BLOCK + tid;
+    if (want_cand & ok[j]) {
+      const long long q = qoff + v;
+      A.c_phi[q] = inside ? phi : __builtin_inff();
+      A.c_nrm[q] = nx;
+      A.c_nrm[A.Q + q] = ny;
+      A.c_nrm[2 * A.Q + q] = nz;
+      A.c_bin[q] = (int16_t)bin;
+    }
+    if (fused) wave_bin_max(cand, bin, make_key(-phi, (unsigned)v), s_keys);
+  }
+}
+
+template <int BLOCK, int VPT>
+__device__ __forceinline__ void reduce_item(const FwdArgs& A, const Item& it, unsigned long long* s_keys) {
+  const long long qoff = A.envs[it.env].qoff;
+  const int tid = threadIdx.x;
+  const int vend = it.vstart + it.vcount;
+  int b[VPT];
+  float phi[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int v = it.vstart + j * BLOCK + tid;
+    b[j] = -1;
+    phi[j] = 0.f;
+    if (v < vend) {
+      b[j] = A.c_bin[qoff + v];
+      phi[j] = A.c_phi[qoff + v];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int v = it.vstart + j * BLOCK + tid;
+    const bool cand = (b[j] >= 0) & (b[j] < A.K);  // bins come from caller memory: stay inside s_keys
+    wave_bin_max(cand, b[j], make_key(-phi[j], (unsigned)v), s_keys);
+  }
+}
+
+// Winner slot of (env, bin = lane): point recomputed from pose and vertex;
+// normal recomputed (fused) or read from the candidates (unfused).
+template <int DT, int LAYOUT>
+__device__ __forceinline__ void write_slot(const FwdArgs& A, int gm, int e, int lane, unsigned long long key,
+                                           bool from_cand) {
+  const long long S = (long long)A.n_env * A.K;
+  const long long s = (long long)e * A.K + lane;
+  if (key == 0ull) {
+    A.o_vidx[s] = -1;
+    A.o_depth[s] = 0.f;
+    A.o_point[s] = 0.f;
+    A.o_point[S + s] = 0.f;
+    A.o_point[2 * S + s] = 0.f;
+    A.o_nrm[s] = 0.f;
+    A.o_nrm[S + s] = 0.f;
+    A.o_nrm[2 * S + s] = 0.f;
+    return;
+  }
+  const unsigned v = key_vidx(key);
+  const MeshDev& m = A.meshes[gm >> 8];
+  if (v >= (unsigned)m.n) {  // only a workspace that was not zeroed can hold such a key
+    A.o_vidx[s] = -1;
+    return;
+  }
+  const Rigid P = load_pose(A.pose, A.n_env, e);
+  float xb, yb, zb;
+  transform(P, m.x[v], m.y[v], m.z[v], xb, yb, zb);
+  float nx, ny, nz;
+  if (from_cand) {
+    const long long q = A.envs[e].qoff + v;
+    nx = A.c_nrm[q];
+    ny = A.c_nrm[A.Q + q];
+    nz = A.c_nrm[2 * A.Q + q];
+  } else {
+    float phi, gx, gy, gz;
+    bool inside;
+    sample<DT, LAYOUT>(A.grids[gm & 0xff], xb, yb, zb, phi, gx, gy, gz, inside);
+    normalize(gx, gy, gz, nx, ny, nz);
+  }
+  A.o_vidx[s] = (int)v;
+  A.o_depth[s] = key_depth(key);
+  A.o_point[s] = xb;
+  A.o_point[S + s] = yb;
+  A.o_point[2 * S + s] = zb;
+  A.o_nrm[s] = nx;
+  A.o_nrm[S + s] = ny;
+  A.o_nrm[2 * S + s] = nz;
+}
+
+// Push a work item's per-bin maxima to its environment's keys.  Relaxed
+// device-scope 64-bit atomics and no fence: the keys are consumed by the next
+// kernel on the stream, after the kernel boundary.
+__device__ __forceinline__ void item_flush(const FwdArgs& A, const Item& it, const unsigned long long* s_keys) {
+  if ((int)threadIdx.x < A.K) {
+    const unsigned long long k = s_keys[threadIdx.x];
+    if (k) atomicMax(&A.keys[(long long)it.env * A.K + threadIdx.x], k);
+  }
+}
+
+template <int DT, int LAYOUT, int BLOCK, int VPT>
+__global__ __launch_bounds__(BLOCK) void k_forward(FwdArgs A, int persistent, int from_cand) {
+  __shared__ unsigned long long s_keys[FC_MAX_BINS];
+  __shared__ int s_item;
+  const bool fused = A.o_vidx != nullptr;
+  int idx;
+  if (persistent == 2) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&A.work_ctr[0], 1u);
+    __syncthreads();
+    idx = s_item;
+    __syncthreads();
+  } else {
+    idx = blockIdx.x;
+  }
+  while (idx < A.n_items) {
+    const Item it = A.items[idx];
+    if (fused) {
+      if (threadIdx.x < FC_MAX_BINS) s_keys[threadIdx.x] = 0ull;
+      __syncthreads();
+    }
+    if (from_cand)
+      reduce_item<BLOCK, VPT>(A, it, s_keys);
+    else
+      query_item<DT, LAYOUT, BLOCK, VPT>(A, it, s_keys, fused);
+    if (fused) {
+      __syncthreads();
+      item_flush(A, it, s_keys);
+      __syncthreads();
+    }
+    if (persistent == 0) break;
+    if (persistent == 1) {
+      idx += gridDim.x;
+    } else {
+      if (threadIdx.x == 0) s_item = (int)atomicAdd(&A.work_ctr[0], 1u);
+      __syncthreads();
+      idx = s_item;
+      __syncthreads();
+    }
+  }
+}
+
+// Winners: one wavefront per environment, lane = bin.  Takes each key
+// (resetting it to zero for the next call), writes the slot and the count,
+// and resets the persistent work counter.
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(256) void k_payload(FwdArgs A, int from_cand) {
+  if (blockIdx.x == 0 && threadIdx.x < 2) A.work_ctr[threadIdx.x] = 0u;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= A.n_env) return;
+  unsigned long long key = 0ull;
+  if (lane < A.K) {
+    unsigned long long* kp = A.keys + (long long)e * A.K + lane;
+    key = *kp;
+    *kp = 0ull;
+    write_slot<DT, LAYOUT>(A, A.envs[e].gm, e, lane, key, from_cand != 0);
+  }
+  const unsigned long long nonempty = __ballot((lane < A.K) && (key != 0ull));
+  if (lane == 0) A.o_count[e] = __popcll(nonempty);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the penetration penalty
+// ---------------------------------------------------------------------------
+// Neumaier compensated accumulation, (sum, compensation) in a float2.
+__device__ __forceinline__ void nadd(float2& a, float x) {
+  const float t = a.x + x;
+  a.y += (fabsf(a.x) >= fabsf(x)) ? ((a.x - t) + x) : ((x - t) + a.x);
+  a.x = t;
+}
+__device__ __forceinline__ float2 ncombine(float2 a, float2 b) {
+  const float t = a.x + b.x;
+  const float e = (fabsf(a.x) >= fabsf(b.x)) ? ((a.x - t) + b.x) : ((b.x - t) + a.x);
+  return make_float2(t, (a.y + b.y) + e);
+}
+
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
+  constexpr int V = kBwdTile / kBwdBlock;
+  constexpr int NW = kBwdBlock / 64;
+  __shared__ float2 s_red[NW][8];
+  const BwdItem it = A.items[blockIdx.x];
+  const BwdChunk ch = A.chunks[it.chunk];
+  const GridDev& g = A.grids[it.gm & 0xff];
+  const MeshDev& m = A.meshes[it.gm >> 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool shared_v = (A.d_verts != nullptr) && !A.per_env;
+
+  float vx[V], vy[V], vz[V];
+  bool ok[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const int v = it.vstart + j * kBwdBlock + tid;
+    ok[j] = v < it.vstart + it.vcount;
+    vx[j] = ok[j] ? m.x[v] : 0.f;
+    vy[j] = ok[j] ? m.y[v] : 0.f;
+    vz[j] = ok[j] ? m.z[v] : 0.f;
+  }
+  float2 accv[V][3];
+#pragma unroll
+  for (int j = 0; j < V; ++j) accv[j][0] = accv[j][1] = accv[j][2] = make_float2(0.f, 0.f);
+
+  for (int c = 0; c < ch.len; ++c) {
+    const int e = A.env_list[ch.first + c];
+    const Rigid P = load_pose(A.pose, A.n_env, e);
+    const float up = A.upstream ? A.upstream[e] : 1.f;
+    float2 acc[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i] = make_float2(0.f, 0.f);
+    bool any = false;
+    float xb[V], yb[V], zb[V];
+    Cell cl[V];
+    float cc[V][8];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      transform(P, vx[j], vy[j], vz[j], xb[j], yb[j], zb[j]);
+      cl[j] = locate(g, xb[j], yb[j], zb[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) gather<DT, LAYOUT>(g, cl[j], cc[j]);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      float phi, gx, gy, gz;
+      trilinear(cc[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
+      const bool act = ok[j] & cl[j].inside & (phi < 0.f);
+      float dvx = 0.f, dvy = 0.f, dvz = 0.f;
+      if (act) {
+        any = true;
+        const float kphi = A.k * phi;
+        const float s = kphi * g.inv_h;  // k phi / h: grid-unit gradient -> metres
+        const float wx = s * gx, wy = s * gy, wz = s * gz;
+        const float mx = fmaf(yb[j], wz, -(zb[j] * wy));
+        const float my = fmaf(zb[j], wx, -(xb[j] * wz));
+        const float mz = fmaf(xb[j], wy, -(yb[j] * wx));
+        nadd(acc[0], 0.5f * kphi * phi);
+        nadd(acc[1], wx);
+        nadd(acc[2], wy);
+        nadd(acc[3], wz);
+        nadd(acc[4], mx);
+        nadd(acc[5], my);
+        nadd(acc[6], mz);
+        // R^T w, scaled by the upstream gradient
+        dvx = up * fmaf(P.r00, wx, fmaf(P.r10, wy, P.r20 * wz));
+        dvy = up * fmaf(P.r01, wx, fmaf(P.r11, wy, P.r21 * wz));
+        dvz = up * fmaf(P.r02, wx, fmaf(P.r12, wy, P.r22 * wz));
+        if (shared_v) {
+          nadd(accv[j][0], dvx);
+          nadd(accv[j][1], dvy);
+          nadd(accv[j][2], dvz);
+        }
+      }
+      if (A.per_env && A.d_verts && ok[j]) {
+        const long long q = A.envs[e].qoff + it.vstart + j * kBwdBlock + tid;
+        A.d_verts[q] = dvx;
+        A.d_verts[A.Q + q] = dvy;
+        A.d_verts[2 * A.Q + q] = dvz;
+      }
+    }
+    // fixed-shape reduction: butterfly within each wave, then waves in order
+    if (__ballot(any) != 0ull) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          float2 o;
+          o.x = __shfl_xor(acc[i].x, off);
+          o.y = __shfl_xor(acc[i].y, off);
+          acc[i] = ncombine(acc[i], o);
+        }
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) s_red[wave][i] = acc[i];
+    }
+    __syncthreads();
+    if (tid < 7) {
+      float2 r = s_red[0][tid];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) r = ncombine(r, s_red[w][tid]);
+      A.pose_part[(long long)(A.env_tile_base[e] + it.tile_in_mesh) * 8 + tid] = r;
+    }
+    __syncthreads();
+  }
+
+  if (shared_v) {
+    const long long base = A.chunks[it.chunk].vpart;
+    const int n = m.n;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      if (!ok[j]) continue;
+      const int v = it.vstart + j * kBwdBlock + tid;
+      A.vert_part[base + v] = accv[j][0];
+      A.vert_part[base + n + v] = accv[j][1];
+      A.vert_part[base + 2 * (long long)n + v] = accv[j][2];
+    }
+  }
+
+}
+
+// Fixed-order combine of the adjoint's partial sums: one thread per
+// (env, value) for the loss and twist, then one per (mesh vertex) for the
+// shared vertex gradients.  Summation order: tiles in order, chunks in order.
+__global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n_pose = (long long)A.n_env * 7;
+  if (i < n_pose) {
+    const int e = (int)(i / 7);
+    const int val = (int)(i - (long long)e * 7);
+    const int n_tiles = A.mesh_tiles[A.envs[e].gm >> 8];
+    const float2* part = A.pose_part + (long long)A.env_tile_base[e] * 8 + val;
+    float2 r = part[0];
+    for (int t = 1; t < n_tiles; ++t) r = ncombine(r, part[(long long)t * 8]);
+    const float v = r.x + r.y;
+    if (val == 0) {
+      if (A.loss) A.loss[e] = v;
+    } else if (A.d_pose) {
+      const float up = A.upstream ? A.upstream[e] : 1.f;
+      A.d_pose[(long long)(val - 1) * A.n_env + e] = up * v;
+    }
+    return;
+  }
+  if (!shared_v) return;
+  long long j = i - n_pose;
+  int m = 0;
+  while (m < A.n_meshes && j >= A.meshes[m].n) {
+    j -= A.meshes[m].n;
+    ++m;
+  }
+  if (m >= A.n_meshes) return;
+  const int n = A.meshes[m].n;
+  float* out = A.d_verts + A.mesh_voff[m];
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    float2 r = make_float2(0.f, 0.f);
+    for (int c = 0; c < A.mesh_nchunks[m]; ++c) {
+      const float2 p = A.vert_part[A.chunks[A.mesh_chunk0[m] + c].vpart + (long long)comp * n + j];
+      r = (c == 0) ? p : ncombine(r, p);
+    }
+    out[(long long)comp * n + j] = r.x + r.y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+// zero n32 32-bit words (4-byte aligned)
+__global__ void k_zero(unsigned* __restrict__ p, size_t n32) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n32; i += stride) p[i] = 0u;
+}
+
+template <typename T>
+__global__ void k_to_bricks(const T* __restrict__ src, T* __restrict__ dst, int nx, int ny, int nz, int bx, int by,
+                            int bz) {
+  constexpr int NB = kBrickNodes * kBrickNodes * kBrickNodes;
+  const long long total = (long long)bx * by * bz * NB;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const long long brick = i / NB;
+    const int local = (int)(i - brick * NB);
+    const int lx = local % kBrickNodes, ly = (local / kBrickNodes) % kBrickNodes, lz = local / (kBrickNodes * kBrickNodes);
+    const int bxi = (int)(brick % bx), byi = (int)((brick / bx) % by), bzi = (int)(brick / ((long long)bx * by));
+    const int x = min(bxi * kBrickCells + lx, nx - 1);
+    const int y = min(byi * kBrickCells + ly, ny - 1);
+    const int z = min(bzi * kBrickCells + lz, nz - 1);
+    dst[i] = src[((long long)z * ny + y) * nx + x];
+  }
+}
+
+template <int DT, int LAYOUT, int BLOCK, int VPT>
+hipError_t fwd_launch(const FwdArgs& a, int persistent, int grid, bool from_cand, hipStream_t s) {
+  hipLaunchKernelGGL((k_forward<DT, LAYOUT, BLOCK, VPT>), dim3(grid), dim3(BLOCK), 0, s, a, persistent,
+                     from_cand ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.o_vidx) {
+    hipLaunchKernelGGL((k_payload<DT, LAYOUT>), dim3((a.n_env + 3) / 4), dim3(256), 0, s, a, from_cand ? 1 : 0);
+    return hipGetLastError();
+  }
+  if (persistent == 2) return launch_zero(a.work_ctr, 2 * sizeof(unsigned), s);
+  return hipSuccess;
+}
+
+template <int DT, int LAYOUT, int BLOCK>
+hipError_t fwd_vpt(const FwdArgs& a, int vpt, int persistent, int grid, bool from_cand, hipStream_t s) {
+  switch (vpt) {
+    case 1: return fwd_launch<DT, LAYOUT, BLOCK, 1>(a, persistent, grid, from_cand, s);
+    case 2: return fwd_launch<DT, LAYOUT, BLOCK, 2>(a, persistent, grid, from_cand, s);
+    case 4: return fwd_launch<DT, LAYOUT, BLOCK, 4>(a, persistent, grid, from_cand, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DT, int LAYOUT>
+hipError_t fwd_block(const FwdArgs& a, int block, int vpt, int persistent, int grid, bool from_cand, hipStream_t s) {
+  switch (block) {
+    case 128: return fwd_vpt<DT, LAYOUT, 128>(a, vpt, persistent, grid, from_cand, s);
+    case 256: return fwd_vpt<DT, LAYOUT, 256>(a, vpt, persistent, grid, from_cand, s);
+    case 512: return fwd_vpt<DT, LAYOUT, 512>(a, vpt, persistent, grid, from_cand, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DT>
+hipError_t fwd_layout(const FwdArgs& a, int layout, int block, int vpt, int persistent, int grid, bool from_cand,
+                      hipStream_t s) {
+  if (layout == FC_LAYOUT_BRICK) return fwd_block<DT, FC_LAYOUT_BRICK>(a, block, vpt, persistent, grid, from_cand, s);
+  return fwd_block<DT, FC_LAYOUT_LINEAR>(a, block, vpt, persistent, grid, from_cand, s);
+}
+
+template <int DT, int LAYOUT>
+hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_backward<DT, LAYOUT>), dim3(a.n_items), dim3(kBwdBlock), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int shared_v = (a.d_verts != nullptr) && !a.per_env;
+  long long n = (long long)a.n_env * 7;
+  if (shared_v)
+    for (int m = 0; m < a.n_meshes; ++m) n += a.meshes[m].n;
+  hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, shared_v);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool forward_shape_supported(int block, int vpt) {
+  return (block == 128 || block == 256 || block == 512) && (vpt == 1 || vpt == 2 || vpt == 4);
+}
+
+hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent, int grid,
+                          bool from_cand, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  // the reduction-from-candidates pass never reads the grid: one instantiation serves every dtype
+  if (from_cand) return fwd_layout<kF32>(a, FC_LAYOUT_LINEAR, block, vpt, persistent, grid, true, s);
+  switch (dtype) {
+    case kF32: return fwd_layout<kF32>(a, layout, block, vpt, persistent, grid, false, s);
+    case kF16: return fwd_layout<kF16>(a, layout, block, vpt, persistent, grid, false, s);
+    case kBF16: return fwd_layout<kBF16>(a, layout, block, vpt, persistent, grid, false, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  const bool brick = layout == FC_LAYOUT_BRICK;
+  switch (dtype) {
+    case kF32: return brick ? bwd_launch<kF32, FC_LAYOUT_BRICK>(a, s) : bwd_launch<kF32, FC_LAYOUT_LINEAR>(a, s);
+    case kF16: return brick ? bwd_launch<kF16, FC_LAYOUT_BRICK>(a, s) : bwd_launch<kF16, FC_LAYOUT_LINEAR>(a, s);
+    case kBF16: return brick ? bwd_launch<kBF16, FC_LAYOUT_BRICK>(a, s) : bwd_launch<kBF16, FC_LAYOUT_LINEAR>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if ((bytes & 3u) || (((uintptr_t)p) & 3u)) return hipErrorInvalidValue;
+  const size_t n32 = bytes / 4;
+  size_t blocks = (n32 + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<unsigned*>(p), n32);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bricks(const void* src, void* dst, int elem, int nx, int ny, int nz, int bx, int by, int bz,
+                            hipStream_t s) {
+  const long long total = (long long)bx * by * bz * kBrickNodes * kBrickNodes * kBrickNodes;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65535) blocks = 65535;
+  if (blocks < 1) blocks = 1;
+  if (elem == 4)
+    hipLaunchKernelGGL(k_to_bricks<float>, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const float*>(src),
+                       static_cast<float*>(dst), nx, ny, nz, bx, by, bz);
+  else
+    hipLaunchKernelGGL(k_to_bricks<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const uint16_t*>(src), static_cast<uint16_t*>(dst), nx, ny, nz, bx, by, bz);
+  return hipGetLastError();
+}
+
+}  // namespace fcimpl

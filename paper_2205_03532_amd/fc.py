@@ -1,0 +1,330 @@
+"""ctypes binding of libfactory_sdf.so (include/fc.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+PyTorch supplies device memory (tensors) and the current stream.  The module
+fails loudly when the library is not built; there is no CPU fallback.
+
+Names follow the C ABI: ``fc_sdf_query``, ``fc_contact_reduce``,
+``fc_sdf_query_backward``, ``fc_graph_create`` / ``fc_graph_launch``,
+``fc_grid_to_bricks``, ``fc_autotune_load``.  ``Batch`` owns the device copies
+of a workload's grids and meshes and the opaque ``fc_batch`` handle.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfactory_sdf.so")
+
+FC_OK, FC_ERR_NULL, FC_ERR_SHAPE, FC_ERR_DTYPE, FC_ERR_RANGE, FC_ERR_WORKSPACE, FC_ERR_HIP, FC_ERR_UNSUPPORTED = range(8)
+DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
+LAYOUTS = {"linear": 0, "brick": 1}
+MAX_TYPES = 8
+MAX_BINS = 64
+
+
+class fc_grid(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("layout", C.c_int32), ("nx", C.c_int32),
+                ("ny", C.c_int32), ("nz", C.c_int32), ("origin", C.c_float * 3), ("h", C.c_float)]
+
+
+class fc_mesh(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("n_verts", C.c_int32)]
+
+
+class fc_batch_desc(C.Structure):
+    _fields_ = [("n_env", C.c_int32), ("grids", C.POINTER(fc_grid)), ("n_grids", C.c_int32),
+                ("meshes", C.POINTER(fc_mesh)), ("n_meshes", C.c_int32), ("env_grid", C.POINTER(C.c_int32)),
+                ("env_mesh", C.POINTER(C.c_int32)), ("n_bins", C.c_int32), ("bin_dirs", C.POINTER(C.c_float)),
+                ("margin", C.c_float)]
+
+
+class fc_candidates(C.Structure):
+    _fields_ = [("phi", C.c_void_p), ("normal", C.c_void_p), ("bin", C.c_void_p)]
+
+
+class fc_contacts(C.Structure):
+    _fields_ = [("vidx", C.c_void_p), ("depth", C.c_void_p), ("point", C.c_void_p), ("normal", C.c_void_p),
+                ("count", C.c_void_p)]
+
+
+class fc_grads(C.Structure):
+    _fields_ = [("loss", C.c_void_p), ("d_pose", C.c_void_p), ("d_verts", C.c_void_p),
+                ("verts_per_env", C.c_int32)]
+
+
+class fc_launch(C.Structure):
+    _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("persistent", C.c_int32), ("grid_mult", C.c_int32)]
+
+
+# every symbol include/fc.h declares, with its ctypes signature
+SIGNATURES = {
+    "fc_batch_create": (C.c_int, [C.POINTER(fc_batch_desc), C.POINTER(C.c_void_p)]),
+    "fc_batch_destroy": (None, [C.c_void_p]),
+    "fc_batch_queries": (C.c_int64, [C.c_void_p]),
+    "fc_batch_set_launch": (C.c_int, [C.c_void_p, C.POINTER(fc_launch)]),
+    "fc_batch_get_launch": (C.c_int, [C.c_void_p, C.POINTER(fc_launch)]),
+    "fc_workspace_bytes": (C.c_size_t, [C.c_void_p]),
+    "fc_workspace_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fc_sdf_query": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_candidates), C.POINTER(fc_contacts),
+                               C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fc_contact_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_candidates), C.POINTER(fc_contacts),
+                                    C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fc_sdf_query_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.POINTER(fc_grads),
+                                        C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fc_graph_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_contacts), C.c_float, C.c_void_p,
+                                  C.POINTER(fc_grads), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "fc_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fc_graph_destroy": (None, [C.c_void_p]),
+    "fc_grid_brick_bytes": (C.c_size_t, [C.POINTER(fc_grid)]),
+    "fc_grid_to_bricks": (C.c_int, [C.POINTER(fc_grid), C.c_void_p, C.c_size_t, C.POINTER(fc_grid), C.c_void_p]),
+    "fc_autotune_load": (C.c_int32, [C.c_char_p]),
+    "fc_batch_signature": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32]),
+    "fc_status_str": (C.c_char_p, [C.c_int]),
+    "fc_last_hip_error": (C.c_int32, []),
+    "fc_version": (C.c_char_p, []),
+}
+
+_LIB = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2205_03532_amd.build` "
+                               "(or __graft_entry__.build()); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+class FcError(RuntimeError):
+    def __init__(self, status, what):
+        L = lib()
+        msg = L.fc_status_str(status).decode()
+        if status == FC_ERR_HIP:
+            msg += f" (hipError {L.fc_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [status {status}]")
+        self.status = status
+
+
+def _check(status, what):
+    if status != FC_OK:
+        raise FcError(status, what)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Batch:
+    """A batch of environments resident on one GPU.
+
+    Holds device tensors of the grids and meshes (SoA), the bin table, the
+    opaque fc_batch, and a zero-initialised workspace.
+    """
+
+    def __init__(self, grids, meshes, env_grid, env_mesh, bins, margin, device="cuda", layout="linear"):
+        import torch
+
+        L = lib()
+        self.device = torch.device(device)
+        self.n_env = int(len(env_grid))
+        self.K = int(bins.shape[1])
+        self._keep = []
+        gdesc = (fc_grid * len(grids))()
+        self.grid_tensors = []
+        for i, g in enumerate(grids):
+            vals = np.ascontiguousarray(g.values)
+            if g.dtype == "f32":
+                t = torch.from_numpy(vals.astype(np.float32, copy=False)).to(self.device)
+            else:
+                t = torch.from_numpy(vals.view(np.int16)).to(self.device)
+            nz, ny, nx = vals.shape
+            d = fc_grid(C.c_void_p(t.data_ptr()), DTYPES[g.dtype], 0, nx, ny, nz,
+                        (C.c_float * 3)(*[float(np.float32(o)) for o in g.origin]), float(np.float32(g.h)))
+            if layout == "brick":
+                nb = L.fc_grid_brick_bytes(C.byref(d))
+                if nb == 0:
+                    raise ValueError("grid cannot be bricked")
+                bt = torch.empty(nb, dtype=torch.uint8, device=self.device)
+                out = fc_grid()
+                _check(L.fc_grid_to_bricks(C.byref(d), C.c_void_p(bt.data_ptr()), nb, C.byref(out),
+                                           _stream(None)), "fc_grid_to_bricks")
+                torch.cuda.synchronize(self.device)
+                self._keep.append(t)
+                t, d = bt, out
+            gdesc[i] = d
+            self.grid_tensors.append(t)
+        mdesc = (fc_mesh * len(meshes))()
+        self.mesh_tensors = []
+        for i, m in enumerate(meshes):
+            v = np.ascontiguousarray(np.asarray(m.verts, dtype=np.float32).T)  # (3, n)
+            t = torch.from_numpy(v).to(self.device)
+            n = v.shape[1]
+            if n:
+                mdesc[i] = fc_mesh(C.c_void_p(t[0].data_ptr()), C.c_void_p(t[1].data_ptr()),
+                                   C.c_void_p(t[2].data_ptr()), n)
+            else:
+                mdesc[i] = fc_mesh(None, None, None, 0)
+            self.mesh_tensors.append(t)
+        self.mesh_sizes = [int(m.verts.shape[0]) for m in meshes]
+        eg = np.ascontiguousarray(env_grid, dtype=np.int32)
+        em = np.ascontiguousarray(env_mesh, dtype=np.int32)
+        self.env_mesh = em
+        dirs = np.ascontiguousarray(bins, dtype=np.float32)
+        desc = fc_batch_desc(self.n_env, gdesc, len(grids), mdesc, len(meshes),
+                             eg.ctypes.data_as(C.POINTER(C.c_int32)), em.ctypes.data_as(C.POINTER(C.c_int32)),
+                             self.K, dirs.ctypes.data_as(C.POINTER(C.c_float)), float(np.float32(margin)))
+        h = C.c_void_p()
+        _check(L.fc_batch_create(C.byref(desc), C.byref(h)), "fc_batch_create")
+        self.handle = h
+        self.Q = int(L.fc_batch_queries(h))
+        self.ws_bytes = int(L.fc_workspace_bytes(h))
+        self.workspace = torch.zeros(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
+
+    @classmethod
+    def from_workload(cls, w, device="cuda", layout="linear"):
+        return cls(w.grids, w.meshes, w.env_grid, w.env_mesh, w.bins, w.margin, device=device, layout=layout)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.fc_batch_destroy(h)
+            self.handle = None
+
+    # ---- output allocation
+    def new_candidates(self):
+        import torch
+
+        return dict(phi=torch.empty(self.Q, dtype=torch.float32, device=self.device),
+                    normal=torch.empty(3, self.Q, dtype=torch.float32, device=self.device),
+                    bin=torch.empty(self.Q, dtype=torch.int16, device=self.device))
+
+    def new_contacts(self):
+        import torch
+
+        S = self.n_env * self.K
+        return dict(vidx=torch.empty(S, dtype=torch.int32, device=self.device),
+                    depth=torch.empty(S, dtype=torch.float32, device=self.device),
+                    point=torch.empty(3, S, dtype=torch.float32, device=self.device),
+                    normal=torch.empty(3, S, dtype=torch.float32, device=self.device),
+                    count=torch.empty(self.n_env, dtype=torch.int32, device=self.device))
+
+    def new_grads(self, per_env=False, loss=True, d_pose=True, d_verts=True):
+        import torch
+
+        nv = self.Q if per_env else sum(self.mesh_sizes)
+        return dict(loss=torch.empty(self.n_env, dtype=torch.float32, device=self.device) if loss else None,
+                    d_pose=torch.empty(6, self.n_env, dtype=torch.float32, device=self.device) if d_pose else None,
+                    d_verts=(torch.empty(3 * nv, dtype=torch.float32, device=self.device) if d_verts else None),
+                    per_env=bool(per_env))
+
+    def set_launch(self, block=256, tile=1024, persistent=0, grid_mult=8):
+        _check(lib().fc_batch_set_launch(self.handle, C.byref(fc_launch(block, tile, persistent, grid_mult))),
+               "fc_batch_set_launch")
+
+    def get_launch(self):
+        l = fc_launch()
+        _check(lib().fc_batch_get_launch(self.handle, C.byref(l)), "fc_batch_get_launch")
+        return dict(block=l.block, tile=l.tile, persistent=l.persistent, grid_mult=l.grid_mult)
+
+    def signature(self):
+        buf = C.create_string_buffer(1024)
+        lib().fc_batch_signature(self.handle, buf, 1024)
+        return buf.value.decode()
+
+    def reset_workspace(self):
+        _check(lib().fc_workspace_init(self.handle, C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                       _stream(None)), "fc_workspace_init")
+
+
+def _cand_struct(c):
+    return None if c is None else fc_candidates(_ptr(c["phi"]), _ptr(c["normal"]), _ptr(c["bin"]))
+
+
+def _contacts_struct(o):
+    return None if o is None else fc_contacts(_ptr(o["vidx"]), _ptr(o["depth"]), _ptr(o["point"]),
+                                              _ptr(o["normal"]), _ptr(o["count"]))
+
+
+def _grads_struct(g):
+    return fc_grads(_ptr(g.get("loss")), _ptr(g.get("d_pose")), _ptr(g.get("d_verts")),
+                    1 if g.get("per_env") else 0)
+
+
+def _byref(s):
+    return None if s is None else C.byref(s)
+
+
+def fc_sdf_query(batch: Batch, pose, cand=None, fused_out=None, stream=None):
+    cs, os_ = _cand_struct(cand), _contacts_struct(fused_out)
+    _check(lib().fc_sdf_query(batch.handle, _ptr(pose), _byref(cs), _byref(os_),
+                              C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes, _stream(stream)),
+           "fc_sdf_query")
+
+
+def fc_contact_reduce(batch: Batch, pose, cand, out, stream=None):
+    _check(lib().fc_contact_reduce(batch.handle, _ptr(pose), C.byref(_cand_struct(cand)),
+                                   C.byref(_contacts_struct(out)), C.c_void_p(batch.workspace.data_ptr()),
+                                   batch.ws_bytes, _stream(stream)), "fc_contact_reduce")
+
+
+def fc_sdf_query_backward(batch: Batch, pose, k, grads, upstream=None, stream=None):
+    _check(lib().fc_sdf_query_backward(batch.handle, _ptr(pose), float(k), _ptr(upstream),
+                                       C.byref(_grads_struct(grads)), C.c_void_p(batch.workspace.data_ptr()),
+                                       batch.ws_bytes, _stream(stream)), "fc_sdf_query_backward")
+
+
+class Graph:
+    """An instantiated hipGraph of one step (fused forward and/or backward)."""
+
+    def __init__(self, batch: Batch, pose, fused_out=None, k=0.0, grads=None, upstream=None):
+        h = C.c_void_p()
+        os_ = _contacts_struct(fused_out)
+        gs = None if grads is None else _grads_struct(grads)
+        _check(lib().fc_graph_create(batch.handle, _ptr(pose), _byref(os_), float(k), _ptr(upstream),
+                                     _byref(gs), C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes,
+                                     C.byref(h)), "fc_graph_create")
+        self.handle = h
+        self._refs = (batch, pose, fused_out, grads, upstream)
+
+    def launch(self, stream=None):
+        _check(lib().fc_graph_launch(self.handle, _stream(stream)), "fc_graph_launch")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.fc_graph_destroy(h)
+            self.handle = None
+
+
+def fc_graph_create(batch, pose, fused_out=None, k=0.0, grads=None, upstream=None) -> Graph:
+    return Graph(batch, pose, fused_out, k, grads, upstream)
+
+
+def fc_autotune_load(path: str) -> int:
+    return int(lib().fc_autotune_load(path.encode()))
+
+
+def pose_tensor(pose_np, device="cuda"):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(pose_np, dtype=np.float32)).to(device)

@@ -1,0 +1,130 @@
+"""The C ABI without a GPU: the library loads, exports every function
+include/fc.h declares, and rejects invalid arguments before any HIP call."""
+import ctypes as C
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2205_03532_amd import fc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fc.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(fc.LIB_PATH):
+        pytest.fail("libfactory_sdf.so not built (run __graft_entry__.build())")
+    return fc.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s+(fc_[a-z_0-9]+)\s*\(", text, flags=re.M))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("fc_sdf_query", "fc_contact_reduce", "fc_sdf_query_backward", "fc_graph_create",
+                     "fc_workspace_bytes", "fc_autotune_load", "fc_status_str", "fc_last_hip_error"):
+        assert required in names
+    assert set(names) == set(fc.SIGNATURES), set(names) ^ set(fc.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.fc_version()
+
+
+def test_status_strings(L):
+    for s in range(8):
+        assert L.fc_status_str(s)
+    assert L.fc_status_str(0) == b"ok"
+
+
+FAKE = 0x100000  # never dereferenced: validation only reads host arrays
+
+
+def make_desc(n_env=2, K=16, dims=(4, 4, 4), h=0.1, dtype=0, n_verts=5, env_grid=None, mesh_null=False,
+              second_grid_dtype=None):
+    grids = (fc.fc_grid * 2)()
+    grids[0] = fc.fc_grid(C.c_void_p(FAKE), dtype, 0, *dims, (C.c_float * 3)(0, 0, 0), h)
+    grids[1] = fc.fc_grid(C.c_void_p(FAKE), dtype if second_grid_dtype is None else second_grid_dtype, 0, *dims,
+                          (C.c_float * 3)(0, 0, 0), h)
+    meshes = (fc.fc_mesh * 1)()
+    p = None if mesh_null else C.c_void_p(FAKE)
+    meshes[0] = fc.fc_mesh(p, p, p, n_verts)
+    eg = np.zeros(n_env, np.int32) if env_grid is None else np.asarray(env_grid, np.int32)
+    em = np.zeros(n_env, np.int32)
+    dirs = np.zeros((3, max(K, 1)), np.float32)
+    dirs[2] = 1
+    desc = fc.fc_batch_desc(n_env, grids, 2, meshes, 1, eg.ctypes.data_as(C.POINTER(C.c_int32)),
+                            em.ctypes.data_as(C.POINTER(C.c_int32)), K, dirs.ctypes.data_as(C.POINTER(C.c_float)),
+                            0.0)
+    desc._keep = (grids, meshes, eg, em, dirs)
+    return desc
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_env=0), fc.FC_ERR_SHAPE),
+    (dict(K=0), fc.FC_ERR_RANGE),
+    (dict(K=65), fc.FC_ERR_RANGE),
+    (dict(dims=(1, 4, 4)), fc.FC_ERR_SHAPE),
+    (dict(dims=(2048, 2048, 1024)), fc.FC_ERR_SHAPE),
+    (dict(h=0.0), fc.FC_ERR_RANGE),
+    (dict(h=float("nan")), fc.FC_ERR_RANGE),
+    (dict(dtype=7), fc.FC_ERR_DTYPE),
+    (dict(second_grid_dtype=1), fc.FC_ERR_DTYPE),
+    (dict(env_grid=[0, 2]), fc.FC_ERR_SHAPE),
+    (dict(env_grid=[-1, 0]), fc.FC_ERR_SHAPE),
+    (dict(n_verts=-1), fc.FC_ERR_SHAPE),
+    (dict(mesh_null=True), fc.FC_ERR_NULL),
+])
+def test_batch_create_rejects(L, kw, status):
+    desc = make_desc(**kw)
+    h = C.c_void_p(12345)
+    assert L.fc_batch_create(C.byref(desc), C.byref(h)) == status
+    assert h.value is None  # nothing handed out
+
+
+def test_null_arguments(L):
+    h = C.c_void_p()
+    assert L.fc_batch_create(None, C.byref(h)) == fc.FC_ERR_NULL
+    assert L.fc_batch_create(C.byref(make_desc()), None) == fc.FC_ERR_NULL
+    assert L.fc_sdf_query(None, None, None, None, None, 0, None) == fc.FC_ERR_NULL
+    assert L.fc_contact_reduce(None, None, None, None, None, 0, None) == fc.FC_ERR_NULL
+    assert L.fc_sdf_query_backward(None, None, 1.0, None, None, None, 0, None) == fc.FC_ERR_NULL
+    assert L.fc_graph_launch(None, None) == fc.FC_ERR_NULL
+    assert L.fc_batch_queries(None) == -1
+    assert L.fc_workspace_bytes(None) == 0
+    L.fc_batch_destroy(None)
+    L.fc_graph_destroy(None)
+
+
+def test_brick_size_query(L):
+    g = fc.fc_grid(C.c_void_p(FAKE), 0, 0, 256, 256, 512, (C.c_float * 3)(0, 0, 0), 1e-4)
+    bx, by, bz = -(-255 // 3), -(-255 // 3), -(-511 // 3)
+    assert L.fc_grid_brick_bytes(C.byref(g)) == bx * by * bz * 64 * 4
+    g.dtype = 1
+    assert L.fc_grid_brick_bytes(C.byref(g)) == bx * by * bz * 64 * 2
+    g.nx = 1
+    assert L.fc_grid_brick_bytes(C.byref(g)) == 0
+
+
+def test_autotune_cache_parse(L, tmp_path):
+    p = tmp_path / "tune.json"
+    p.write_text(json.dumps({"entries": [
+        {"key": "a", "block": 256, "tile": 1024, "persistent": 0, "grid_mult": 8},
+        {"key": "b", "block": 128, "tile": 512, "persistent": 2, "grid_mult": 4},
+        {"key": "bad", "block": 100, "tile": 1024, "persistent": 0, "grid_mult": 8},
+    ]}))
+    assert L.fc_autotune_load(str(p).encode()) == 2
+    p.write_text("{not json")
+    assert L.fc_autotune_load(str(p).encode()) == -1
+    assert L.fc_autotune_load(b"/nonexistent/file.json") == -1
