@@ -105,6 +105,12 @@ typedef struct fc_batch_desc {
   int32_t n_bins;           /* K, 1 <= K <= FC_MAX_BINS */
   const float* bin_dirs;    /* host [3][K] unit directions d_k (copied) */
   float margin;             /* a query is a candidate iff phi < margin */
+  const int32_t* env_order; /* host [n_env] permutation of 0..n_env-1, or NULL = 0..n_env-1:
+                               the order in which environments are scheduled.  Callers pass a
+                               spatial sort of their envs (e.g. by position in B's frame) so that
+                               work running together reads the same part of the grid.  Contacts
+                               do not depend on it; the shared vertex gradient sums envs in
+                               this order. */
 } fc_batch_desc;
 
 typedef struct fc_batch fc_batch; /* opaque; owns device work tables */
@@ -159,12 +165,15 @@ typedef struct fc_grads {
  *   persistent  0: one workgroup per item; 1: a grid of about
  *               grid_mult workgroups per compute unit pulling items in a
  *               fixed order; 2: the same pulling items from an atomic counter;
- *   grid_mult   workgroups per compute unit for persistent launches (1..32). */
+ *   grid_mult   workgroups per compute unit for persistent launches (1..32);
+ *   xcd_remap   1: split the items into 8 contiguous ranges, one per XCD
+ *               (each XCD has its own L2), for the forward and the adjoint. */
 typedef struct fc_launch {
   int32_t block;
   int32_t tile;
   int32_t persistent;
   int32_t grid_mult;
+  int32_t xcd_remap;
 } fc_launch;
 
 /* ---- set-up ------------------------------------------------------------- */
@@ -253,7 +262,7 @@ fc_status fc_grid_to_bricks(const fc_grid* src, void* dst_data, size_t dst_bytes
 
 /* Load a launch-shape cache written by the autotuner: a JSON object
  * {"entries": [{"key": "<signature>", "block": B, "tile": T,
- * "persistent": P, "grid_mult": M}, ...]}.  Batches created afterwards whose
+ * "persistent": P, "grid_mult": M, "xcd_remap": X}, ...]}.  Batches created afterwards whose
  * signature matches use that shape.  Returns the number of entries loaded,
  * or -1 if the file cannot be read or parsed. */
 int32_t fc_autotune_load(const char* json_path);

@@ -86,6 +86,14 @@ fc_status validate_desc(const fc_batch_desc* d) {
     if (m.n_verts < 0) return FC_ERR_SHAPE;
     if (m.n_verts > 0 && (!m.x || !m.y || !m.z)) return FC_ERR_NULL;
   }
+  if (d->env_order) {
+    std::vector<char> seen(d->n_env, 0);
+    for (int e = 0; e < d->n_env; ++e) {
+      const int o = d->env_order[e];
+      if (o < 0 || o >= d->n_env || seen[o]) return FC_ERR_SHAPE;
+      seen[o] = 1;
+    }
+  }
   long long Q = 0;
   for (int e = 0; e < d->n_env; ++e) {
     const int gi = d->env_grid ? d->env_grid[e] : 0;
@@ -102,6 +110,7 @@ bool launch_valid(const fc_launch& l) {
   if (!forward_shape_supported(l.block, l.tile / l.block)) return false;
   if (l.persistent < 0 || l.persistent > 2) return false;
   if (l.grid_mult < 1 || l.grid_mult > 32) return false;
+  if (l.xcd_remap < 0 || l.xcd_remap > 1) return false;
   return true;
 }
 
@@ -263,10 +272,11 @@ struct fc_batch {
   std::vector<fc_grid> grids;
   std::vector<fc_mesh> meshes;
   std::vector<int> env_grid, env_mesh;
+  std::vector<int> order;  // scheduling order of the envs
   std::vector<float> dirs;
   std::vector<long long> qoff;
   long long Q = 0;
-  fc_launch launch{256, 1024, 0, 8};
+  fc_launch launch{256, 1024, 0, 8, 0};
   int num_cus = 256;
   std::string signature;
   // forward tables
@@ -284,6 +294,7 @@ struct fc_batch {
   int mesh_tiles[FC_MAX_TYPES] = {0};
   int mesh_chunk0[FC_MAX_TYPES] = {0};
   int mesh_nchunks[FC_MAX_TYPES] = {0};
+  long long mesh_vpart0[FC_MAX_TYPES] = {0};
   // workspace layout (bytes)
   size_t off_keys = 0, off_workctr = 0, off_pose = 0, off_vert = 0, ws_bytes = 0;
 };
@@ -311,7 +322,8 @@ fc_status build_forward_tables(fc_batch* b) {
   std::vector<Item> items;
   std::vector<EnvInfo> envs(b->n_env);
   const int tile = b->launch.tile;
-  for (int e = 0; e < b->n_env; ++e) {
+  for (int oi = 0; oi < b->n_env; ++oi) {
+    const int e = b->order[oi];
     const int n = b->meshes[b->env_mesh[e]].n_verts;
     const int ni = n > 0 ? ceil_div(n, tile) : 1;
     envs[e].qoff = b->qoff[e];
@@ -361,10 +373,13 @@ fc_status build_backward_tables(fc_batch* b) {
     b->mesh_voff[m] = voff;
     voff += 3LL * b->meshes[m].n_verts;
     b->mesh_chunk0[m] = (int)chunks.size();
+    b->mesh_vpart0[m] = vpart;
     for (int g = 0; g < (int)b->grids.size(); ++g) {
       std::vector<int> grp;
-      for (int e = 0; e < b->n_env; ++e)
+      for (int oi = 0; oi < b->n_env; ++oi) {
+        const int e = b->order[oi];
         if (b->env_mesh[e] == m && b->env_grid[e] == g) grp.push_back(e);
+      }
       for (size_t i = 0; i < grp.size(); i += kBwdChunk) {
         BwdChunk c;
         c.first = (int)env_list.size();
@@ -403,7 +418,7 @@ fc_status build_backward_tables(fc_batch* b) {
   b->off_keys = off;
   off = align256(off + (size_t)b->n_env * b->K * 8);
   b->off_workctr = off;
-  off = align256(off + 2 * 4);
+  off = align256(off + kXcds * 4);
   b->off_pose = off;
   off = align256(off + (size_t)rows * 8 * sizeof(float2));
   b->off_vert = off;
@@ -471,9 +486,16 @@ FwdArgs make_fwd(const fc_batch* b, const float* pose, const fc_candidates* cand
 }
 
 int forward_grid(const fc_batch* b) {
-  if (b->launch.persistent == 0) return b->n_items;
-  const long long g = (long long)b->num_cus * b->launch.grid_mult;
-  return (int)std::min<long long>(g, b->n_items);
+  const fc_launch& l = b->launch;
+  if (!l.xcd_remap) {
+    if (l.persistent == 0) return b->n_items;
+    return (int)std::min<long long>((long long)b->num_cus * l.grid_mult, b->n_items);
+  }
+  // XCD ranges: the grid is a multiple of kXcds, at most one workgroup per item of a range
+  const long long per = (b->n_items + kXcds - 1) / kXcds;
+  if (l.persistent == 0) return (int)(kXcds * per);
+  const long long slots = std::max<long long>(1, std::min<long long>(per, (long long)b->num_cus * l.grid_mult / kXcds));
+  return (int)(kXcds * slots);
 }
 
 bool contacts_ok(const fc_contacts* o) {
@@ -484,8 +506,8 @@ fc_status enqueue_forward(const fc_batch* b, const float* pose, const fc_candida
                           void* ws, hipStream_t s, bool from_cand) {
   const FwdArgs a = make_fwd(b, pose, cand, out, ws);
   const int vpt = b->launch.tile / b->launch.block;
-  FC_HIP(launch_forward(a, b->dtype, b->layout, b->launch.block, vpt, b->launch.persistent, forward_grid(b),
-                        from_cand, s));
+  FC_HIP(launch_forward(a, b->dtype, b->layout, b->launch.block, vpt, b->launch.persistent, b->launch.xcd_remap,
+                        forward_grid(b), from_cand, s));
   return FC_OK;
 }
 
@@ -499,6 +521,7 @@ fc_status enqueue_backward(const fc_batch* b, const float* pose, float k, const 
     a.mesh_tiles[m] = b->mesh_tiles[m];
     a.mesh_chunk0[m] = b->mesh_chunk0[m];
     a.mesh_nchunks[m] = b->mesh_nchunks[m];
+    a.mesh_vpart0[m] = b->mesh_vpart0[m];
   }
   a.n_meshes = (int)b->meshes.size();
   a.items = b->d_bitems;
@@ -512,6 +535,7 @@ fc_status enqueue_backward(const fc_batch* b, const float* pose, float k, const 
   a.n_env = b->n_env;
   a.k = k;
   a.per_env = out->verts_per_env ? 1 : 0;
+  a.xcd = b->launch.xcd_remap;
   a.Q = b->Q;
   a.loss = out->loss;
   a.d_pose = out->d_pose;
@@ -570,6 +594,8 @@ fc_status fc_batch_create(const fc_batch_desc* desc, fc_batch** out) {
   b->env_mesh.resize(b->n_env);
   b->qoff.resize(b->n_env);
   long long q = 0;
+  b->order.resize(b->n_env);
+  for (int e = 0; e < b->n_env; ++e) b->order[e] = desc->env_order ? desc->env_order[e] : e;
   for (int e = 0; e < b->n_env; ++e) {
     b->env_grid[e] = desc->env_grid ? desc->env_grid[e] : 0;
     b->env_mesh[e] = desc->env_mesh ? desc->env_mesh[e] : 0;
@@ -783,8 +809,10 @@ int32_t fc_autotune_load(const char* path) {
     const JVal* ti = jget(e, "tile");
     const JVal* pe = jget(e, "persistent");
     const JVal* gm = jget(e, "grid_mult");
+    const JVal* xr = jget(e, "xcd_remap");
     if (!key || key->kind != JVal::STR || !bl || !ti || !pe || !gm) continue;
-    fc_launch l{(int32_t)bl->num, (int32_t)ti->num, (int32_t)pe->num, (int32_t)gm->num};
+    fc_launch l{(int32_t)bl->num, (int32_t)ti->num, (int32_t)pe->num, (int32_t)gm->num,
+                xr ? (int32_t)xr->num : 0};
     if (!launch_valid(l)) continue;
     g_tune[key->str] = l;
     ++loaded;

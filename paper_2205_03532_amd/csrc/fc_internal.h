@@ -16,6 +16,9 @@ constexpr int kBwdTile = 512;   // vertices per backward item (pose partial sums
 constexpr int kBwdBlock = 256;  // threads per backward workgroup (2 vertices each)
 constexpr int kBwdChunk = 32;   // environments per backward item (vertex partial sums)
 
+// Dispatch places workgroup i on XCD i mod kXcds (MI355X: 8 XCDs, one L2 each).
+constexpr int kXcds = 8;
+
 // Brick layout: 4x4x4 nodes per brick covering 3x3x3 cells.
 constexpr int kBrickCells = 3;
 constexpr int kBrickNodes = 4;
@@ -73,7 +76,7 @@ struct FwdArgs {
   int* o_count;
   // workspace (zero between calls)
   unsigned long long* keys;  // [n_env][K] per-bin maxima, taken and reset by the payload kernel
-  unsigned* work_ctr;        // [2] persistent work counter, reset by the payload kernel
+  unsigned* work_ctr;        // [kXcds] persistent work counters, reset by the payload kernel
 };
 
 struct BwdItem {
@@ -101,6 +104,7 @@ struct BwdArgs {
   int mesh_tiles[FC_MAX_TYPES];       // backward tiles of mesh m (>= 1)
   int mesh_chunk0[FC_MAX_TYPES];      // first chunk of mesh m (chunks of a mesh are contiguous)
   int mesh_nchunks[FC_MAX_TYPES];     // chunks of mesh m
+  long long mesh_vpart0[FC_MAX_TYPES];  // vertex-partial offset (float2) of mesh m's first chunk
   int n_meshes;
   const BwdItem* items;
   const BwdChunk* chunks;
@@ -113,6 +117,7 @@ struct BwdArgs {
   int n_env;
   float k;
   int per_env;
+  int xcd;  // XCD-contiguous item ranges
   long long Q;
   float* loss;
   float* d_pose;
@@ -123,7 +128,7 @@ struct BwdArgs {
 };
 
 // launch wrappers (fc_kernels.hip)
-hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent,
+hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent, int xcd,
                           int grid, bool from_cand, hipStream_t s);
 hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -385,21 +385,53 @@ __device__ __forceinline__ void item_flush(const FwdArgs& A, const Item& it, con
   }
 }
 
+// Work items a workgroup owns.  Plain launch: item = workgroup id.  With
+// `xcd` set, the items are split into kXcds contiguous ranges and range x is
+// served by the workgroups the dispatcher places on XCD x (ids = x mod kXcds),
+// so each XCD's L2 sees a contiguous stretch of the (locality-ordered) item
+// list.  Persistent launches stride (1) or pull from a per-range atomic
+// counter (2).
+struct ItemRange {
+  int lo, hi, slot, nslots;
+  unsigned* ctr;
+};
+
+__device__ __forceinline__ ItemRange item_range(int n_items, int xcd, unsigned* work_ctr) {
+  ItemRange r;
+  if (xcd) {
+    const int x = blockIdx.x % kXcds;
+    const int per = (n_items + kXcds - 1) / kXcds;
+    r.lo = x * per;
+    r.hi = min(n_items, r.lo + per);
+    r.slot = blockIdx.x / kXcds;
+    r.nslots = gridDim.x / kXcds;
+    r.ctr = work_ctr + x;
+  } else {
+    r.lo = 0;
+    r.hi = n_items;
+    r.slot = blockIdx.x;
+    r.nslots = gridDim.x;
+    r.ctr = work_ctr;
+  }
+  return r;
+}
+
 template <int DT, int LAYOUT, int BLOCK, int VPT>
-__global__ __launch_bounds__(BLOCK) void k_forward(FwdArgs A, int persistent, int from_cand) {
+__global__ __launch_bounds__(BLOCK) void k_forward(FwdArgs A, int persistent, int from_cand, int xcd) {
   __shared__ unsigned long long s_keys[FC_MAX_BINS];
   __shared__ int s_item;
   const bool fused = A.o_vidx != nullptr;
+  const ItemRange R = item_range(A.n_items, xcd, A.work_ctr);
   int idx;
   if (persistent == 2) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(&A.work_ctr[0], 1u);
+    if (threadIdx.x == 0) s_item = R.lo + (int)atomicAdd(R.ctr, 1u);
     __syncthreads();
     idx = s_item;
     __syncthreads();
   } else {
-    idx = blockIdx.x;
+    idx = R.lo + R.slot;
   }
-  while (idx < A.n_items) {
+  while (idx < R.hi) {
     const Item it = A.items[idx];
     if (fused) {
       if (threadIdx.x < FC_MAX_BINS) s_keys[threadIdx.x] = 0ull;
@@ -416,9 +448,9 @@ __global__ __launch_bounds__(BLOCK) void k_forward(FwdArgs A, int persistent, in
     }
     if (persistent == 0) break;
     if (persistent == 1) {
-      idx += gridDim.x;
+      idx += R.nslots;
     } else {
-      if (threadIdx.x == 0) s_item = (int)atomicAdd(&A.work_ctr[0], 1u);
+      if (threadIdx.x == 0) s_item = R.lo + (int)atomicAdd(R.ctr, 1u);
       __syncthreads();
       idx = s_item;
       __syncthreads();
@@ -428,10 +460,10 @@ __global__ __launch_bounds__(BLOCK) void k_forward(FwdArgs A, int persistent, in
 
 // Winners: one wavefront per environment, lane = bin.  Takes each key
 // (resetting it to zero for the next call), writes the slot and the count,
-// and resets the persistent work counter.
+// and resets the persistent work counters.
 template <int DT, int LAYOUT>
 __global__ __launch_bounds__(256) void k_payload(FwdArgs A, int from_cand) {
-  if (blockIdx.x == 0 && threadIdx.x < 2) A.work_ctr[threadIdx.x] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) A.work_ctr[threadIdx.x] = 0u;
   const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (e >= A.n_env) return;
@@ -466,7 +498,14 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
   constexpr int V = kBwdTile / kBwdBlock;
   constexpr int NW = kBwdBlock / 64;
   __shared__ float2 s_red[NW][8];
-  const BwdItem it = A.items[blockIdx.x];
+  int idx = blockIdx.x;
+  if (A.xcd) {  // XCD x serves the x-th contiguous range of items (see item_range)
+    const int per = (A.n_items + kXcds - 1) / kXcds;
+    const int slot = blockIdx.x / kXcds;
+    idx = (blockIdx.x % kXcds) * per + slot;
+    if (slot >= per || idx >= A.n_items) return;
+  }
+  const BwdItem it = A.items[idx];
   const BwdChunk ch = A.chunks[it.chunk];
   const GridDev& g = A.grids[it.gm & 0xff];
   const MeshDev& m = A.meshes[it.gm >> 8];
@@ -586,9 +625,11 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
 }
 
 // Fixed-order combine of the adjoint's partial sums: one thread per
-// (env, value) for the loss and twist, then one per (mesh vertex) for the
-// shared vertex gradients.  Summation order: tiles in order, chunks in order.
-__global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v) {
+// (env, value) for the loss and twist, then one per (component, mesh vertex)
+// for the shared vertex gradients.  Summation order: tiles in order, chunks
+// in order.  Partial offsets are computed, not loaded, so every thread's
+// loads are independent and in flight together.
+__global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, long long n_vert_total) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long n_pose = (long long)A.n_env * 7;
   if (i < n_pose) {
@@ -608,24 +649,24 @@ __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v) {
     return;
   }
   if (!shared_v) return;
-  long long j = i - n_pose;
+  const long long jj = i - n_pose;
+  if (jj >= 3 * n_vert_total) return;
+  const int comp = (int)(jj / n_vert_total);
+  long long j = jj - (long long)comp * n_vert_total;
   int m = 0;
-  while (m < A.n_meshes && j >= A.meshes[m].n) {
+  while (m < A.n_meshes - 1 && j >= A.meshes[m].n) {
     j -= A.meshes[m].n;
     ++m;
   }
-  if (m >= A.n_meshes) return;
-  const int n = A.meshes[m].n;
-  float* out = A.d_verts + A.mesh_voff[m];
-#pragma unroll
-  for (int comp = 0; comp < 3; ++comp) {
-    float2 r = make_float2(0.f, 0.f);
-    for (int c = 0; c < A.mesh_nchunks[m]; ++c) {
-      const float2 p = A.vert_part[A.chunks[A.mesh_chunk0[m] + c].vpart + (long long)comp * n + j];
-      r = (c == 0) ? p : ncombine(r, p);
-    }
-    out[(long long)comp * n + j] = r.x + r.y;
-  }
+  const long long n = A.meshes[m].n;
+  const int nc = A.mesh_nchunks[m];
+  // chunks of mesh m are contiguous and each holds [3][n] partials
+  const float2* p = A.vert_part + A.mesh_vpart0[m] + comp * n + j;
+  const long long stride = 3 * n;
+  float2 r = make_float2(0.f, 0.f);
+  if (nc > 0) r = p[0];
+  for (int c = 1; c < nc; ++c) r = ncombine(r, p[c * stride]);
+  A.d_verts[A.mesh_voff[m] + comp * n + j] = r.x + r.y;
 }
 
 // ---------------------------------------------------------------------------
@@ -656,56 +697,59 @@ __global__ void k_to_bricks(const T* __restrict__ src, T* __restrict__ dst, int 
 }
 
 template <int DT, int LAYOUT, int BLOCK, int VPT>
-hipError_t fwd_launch(const FwdArgs& a, int persistent, int grid, bool from_cand, hipStream_t s) {
+hipError_t fwd_launch(const FwdArgs& a, int persistent, int xcd, int grid, bool from_cand, hipStream_t s) {
   hipLaunchKernelGGL((k_forward<DT, LAYOUT, BLOCK, VPT>), dim3(grid), dim3(BLOCK), 0, s, a, persistent,
-                     from_cand ? 1 : 0);
+                     from_cand ? 1 : 0, xcd);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.o_vidx) {
     hipLaunchKernelGGL((k_payload<DT, LAYOUT>), dim3((a.n_env + 3) / 4), dim3(256), 0, s, a, from_cand ? 1 : 0);
     return hipGetLastError();
   }
-  if (persistent == 2) return launch_zero(a.work_ctr, 2 * sizeof(unsigned), s);
+  if (persistent == 2) return launch_zero(a.work_ctr, kXcds * sizeof(unsigned), s);
   return hipSuccess;
 }
 
 template <int DT, int LAYOUT, int BLOCK>
-hipError_t fwd_vpt(const FwdArgs& a, int vpt, int persistent, int grid, bool from_cand, hipStream_t s) {
+hipError_t fwd_vpt(const FwdArgs& a, int vpt, int persistent, int xcd, int grid, bool from_cand, hipStream_t s) {
   switch (vpt) {
-    case 1: return fwd_launch<DT, LAYOUT, BLOCK, 1>(a, persistent, grid, from_cand, s);
-    case 2: return fwd_launch<DT, LAYOUT, BLOCK, 2>(a, persistent, grid, from_cand, s);
-    case 4: return fwd_launch<DT, LAYOUT, BLOCK, 4>(a, persistent, grid, from_cand, s);
+    case 1: return fwd_launch<DT, LAYOUT, BLOCK, 1>(a, persistent, xcd, grid, from_cand, s);
+    case 2: return fwd_launch<DT, LAYOUT, BLOCK, 2>(a, persistent, xcd, grid, from_cand, s);
+    case 4: return fwd_launch<DT, LAYOUT, BLOCK, 4>(a, persistent, xcd, grid, from_cand, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int DT, int LAYOUT>
-hipError_t fwd_block(const FwdArgs& a, int block, int vpt, int persistent, int grid, bool from_cand, hipStream_t s) {
+hipError_t fwd_block(const FwdArgs& a, int block, int vpt, int persistent, int xcd, int grid, bool from_cand,
+                      hipStream_t s) {
   switch (block) {
-    case 128: return fwd_vpt<DT, LAYOUT, 128>(a, vpt, persistent, grid, from_cand, s);
-    case 256: return fwd_vpt<DT, LAYOUT, 256>(a, vpt, persistent, grid, from_cand, s);
-    case 512: return fwd_vpt<DT, LAYOUT, 512>(a, vpt, persistent, grid, from_cand, s);
+    case 128: return fwd_vpt<DT, LAYOUT, 128>(a, vpt, persistent, xcd, grid, from_cand, s);
+    case 256: return fwd_vpt<DT, LAYOUT, 256>(a, vpt, persistent, xcd, grid, from_cand, s);
+    case 512: return fwd_vpt<DT, LAYOUT, 512>(a, vpt, persistent, xcd, grid, from_cand, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int DT>
-hipError_t fwd_layout(const FwdArgs& a, int layout, int block, int vpt, int persistent, int grid, bool from_cand,
-                      hipStream_t s) {
-  if (layout == FC_LAYOUT_BRICK) return fwd_block<DT, FC_LAYOUT_BRICK>(a, block, vpt, persistent, grid, from_cand, s);
-  return fwd_block<DT, FC_LAYOUT_LINEAR>(a, block, vpt, persistent, grid, from_cand, s);
+hipError_t fwd_layout(const FwdArgs& a, int layout, int block, int vpt, int persistent, int xcd, int grid,
+                      bool from_cand, hipStream_t s) {
+  if (layout == FC_LAYOUT_BRICK)
+    return fwd_block<DT, FC_LAYOUT_BRICK>(a, block, vpt, persistent, xcd, grid, from_cand, s);
+  return fwd_block<DT, FC_LAYOUT_LINEAR>(a, block, vpt, persistent, xcd, grid, from_cand, s);
 }
 
 template <int DT, int LAYOUT>
 hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_backward<DT, LAYOUT>), dim3(a.n_items), dim3(kBwdBlock), 0, s, a);
+  const int grid = a.xcd ? kXcds * ((a.n_items + kXcds - 1) / kXcds) : a.n_items;
+  hipLaunchKernelGGL((k_backward<DT, LAYOUT>), dim3(grid), dim3(kBwdBlock), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int shared_v = (a.d_verts != nullptr) && !a.per_env;
-  long long n = (long long)a.n_env * 7;
-  if (shared_v)
-    for (int m = 0; m < a.n_meshes; ++m) n += a.meshes[m].n;
-  hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, shared_v);
+  long long nv = 0;
+  for (int m = 0; m < a.n_meshes; ++m) nv += a.meshes[m].n;
+  const long long n = (long long)a.n_env * 7 + (shared_v ? 3 * nv : 0);
+  hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, shared_v, nv);
   return hipGetLastError();
 }
 
@@ -715,15 +759,15 @@ bool forward_shape_supported(int block, int vpt) {
   return (block == 128 || block == 256 || block == 512) && (vpt == 1 || vpt == 2 || vpt == 4);
 }
 
-hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent, int grid,
-                          bool from_cand, hipStream_t s) {
+hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent, int xcd,
+                          int grid, bool from_cand, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   // the reduction-from-candidates pass never reads the grid: one instantiation serves every dtype
-  if (from_cand) return fwd_layout<kF32>(a, FC_LAYOUT_LINEAR, block, vpt, persistent, grid, true, s);
+  if (from_cand) return fwd_layout<kF32>(a, FC_LAYOUT_LINEAR, block, vpt, persistent, xcd, grid, true, s);
   switch (dtype) {
-    case kF32: return fwd_layout<kF32>(a, layout, block, vpt, persistent, grid, false, s);
-    case kF16: return fwd_layout<kF16>(a, layout, block, vpt, persistent, grid, false, s);
-    case kBF16: return fwd_layout<kBF16>(a, layout, block, vpt, persistent, grid, false, s);
+    case kF32: return fwd_layout<kF32>(a, layout, block, vpt, persistent, xcd, grid, false, s);
+    case kF16: return fwd_layout<kF16>(a, layout, block, vpt, persistent, xcd, grid, false, s);
+    case kBF16: return fwd_layout<kBF16>(a, layout, block, vpt, persistent, xcd, grid, false, s);
   }
   return hipErrorInvalidValue;
 }

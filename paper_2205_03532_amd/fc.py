@@ -38,7 +38,7 @@ class fc_batch_desc(C.Structure):
     _fields_ = [("n_env", C.c_int32), ("grids", C.POINTER(fc_grid)), ("n_grids", C.c_int32),
                 ("meshes", C.POINTER(fc_mesh)), ("n_meshes", C.c_int32), ("env_grid", C.POINTER(C.c_int32)),
                 ("env_mesh", C.POINTER(C.c_int32)), ("n_bins", C.c_int32), ("bin_dirs", C.POINTER(C.c_float)),
-                ("margin", C.c_float)]
+                ("margin", C.c_float), ("env_order", C.POINTER(C.c_int32))]
 
 
 class fc_candidates(C.Structure):
@@ -56,7 +56,8 @@ class fc_grads(C.Structure):
 
 
 class fc_launch(C.Structure):
-    _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("persistent", C.c_int32), ("grid_mult", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("persistent", C.c_int32), ("grid_mult", C.c_int32),
+                ("xcd_remap", C.c_int32)]
 
 
 # every symbol include/fc.h declares, with its ctypes signature
@@ -139,7 +140,8 @@ class Batch:
     opaque fc_batch, and a zero-initialised workspace.
     """
 
-    def __init__(self, grids, meshes, env_grid, env_mesh, bins, margin, device="cuda", layout="linear"):
+    def __init__(self, grids, meshes, env_grid, env_mesh, bins, margin, device="cuda", layout="linear",
+                 env_order=None):
         import torch
 
         L = lib()
@@ -188,9 +190,11 @@ class Batch:
         em = np.ascontiguousarray(env_mesh, dtype=np.int32)
         self.env_mesh = em
         dirs = np.ascontiguousarray(bins, dtype=np.float32)
+        eo = None if env_order is None else np.ascontiguousarray(env_order, dtype=np.int32)
         desc = fc_batch_desc(self.n_env, gdesc, len(grids), mdesc, len(meshes),
                              eg.ctypes.data_as(C.POINTER(C.c_int32)), em.ctypes.data_as(C.POINTER(C.c_int32)),
-                             self.K, dirs.ctypes.data_as(C.POINTER(C.c_float)), float(np.float32(margin)))
+                             self.K, dirs.ctypes.data_as(C.POINTER(C.c_float)), float(np.float32(margin)),
+                             None if eo is None else eo.ctypes.data_as(C.POINTER(C.c_int32)))
         h = C.c_void_p()
         _check(L.fc_batch_create(C.byref(desc), C.byref(h)), "fc_batch_create")
         self.handle = h
@@ -201,8 +205,9 @@ class Batch:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
 
     @classmethod
-    def from_workload(cls, w, device="cuda", layout="linear"):
-        return cls(w.grids, w.meshes, w.env_grid, w.env_mesh, w.bins, w.margin, device=device, layout=layout)
+    def from_workload(cls, w, device="cuda", layout="linear", env_order=None):
+        return cls(w.grids, w.meshes, w.env_grid, w.env_mesh, w.bins, w.margin, device=device, layout=layout,
+                   env_order=env_order)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -237,14 +242,15 @@ class Batch:
                     d_verts=(torch.empty(3 * nv, dtype=torch.float32, device=self.device) if d_verts else None),
                     per_env=bool(per_env))
 
-    def set_launch(self, block=256, tile=1024, persistent=0, grid_mult=8):
-        _check(lib().fc_batch_set_launch(self.handle, C.byref(fc_launch(block, tile, persistent, grid_mult))),
-               "fc_batch_set_launch")
+    def set_launch(self, block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=0):
+        _check(lib().fc_batch_set_launch(self.handle, C.byref(fc_launch(block, tile, persistent, grid_mult,
+                                                                         xcd_remap))), "fc_batch_set_launch")
 
     def get_launch(self):
         l = fc_launch()
         _check(lib().fc_batch_get_launch(self.handle, C.byref(l)), "fc_batch_get_launch")
-        return dict(block=l.block, tile=l.tile, persistent=l.persistent, grid_mult=l.grid_mult)
+        return dict(block=l.block, tile=l.tile, persistent=l.persistent, grid_mult=l.grid_mult,
+                    xcd_remap=l.xcd_remap)
 
     def signature(self):
         buf = C.create_string_buffer(1024)
@@ -322,6 +328,22 @@ def fc_graph_create(batch, pose, fused_out=None, k=0.0, grads=None, upstream=Non
 
 def fc_autotune_load(path: str) -> int:
     return int(lib().fc_autotune_load(path.encode()))
+
+
+def locality_order(w):
+    """A scheduling order for ``fc_batch_desc.env_order``: envs grouped by
+    part type, then sorted along a Z-order curve of their translation, so that
+    consecutive envs sit near each other in B's frame.  Host-side, from the
+    poses the caller already has."""
+    t = np.asarray(w.pose[4:7], dtype=np.float64).T
+    lo, hi = t.min(axis=0), t.max(axis=0)
+    span = np.where(hi > lo, hi - lo, 1.0)
+    q = np.clip(((t - lo) / span * 1023).astype(np.int64), 0, 1023)
+    code = np.zeros(len(t), dtype=np.int64)
+    for bit in range(10):
+        for a in range(3):
+            code |= ((q[:, a] >> bit) & 1) << (3 * bit + a)
+    return np.lexsort((code, np.asarray(w.env_mesh), np.asarray(w.env_grid))).astype(np.int32)
 
 
 def pose_tensor(pose_np, device="cuda"):

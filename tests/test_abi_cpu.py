@@ -128,3 +128,12 @@ def test_autotune_cache_parse(L, tmp_path):
     p.write_text("{not json")
     assert L.fc_autotune_load(str(p).encode()) == -1
     assert L.fc_autotune_load(b"/nonexistent/file.json") == -1
+
+
+def test_env_order_must_be_a_permutation(L):
+    desc = make_desc(n_env=3)
+    for bad in ([0, 0, 2], [0, 1, 3], [-1, 0, 1]):
+        eo = np.asarray(bad, np.int32)
+        desc.env_order = eo.ctypes.data_as(C.POINTER(C.c_int32))
+        h = C.c_void_p()
+        assert L.fc_batch_create(C.byref(desc), C.byref(h)) == fc.FC_ERR_SHAPE

@@ -128,6 +128,25 @@ def test_adjoint_deterministic_and_workspace_clean(nutbolt40):
     assert_same(r1, r2)
 
 
+def test_adjoint_xcd_ranges_and_env_order(nutbolt40):
+    """XCD-range scheduling leaves every output bit-identical; a different env
+    order changes only the shared vertex sum's rounding."""
+    w, b, pose = nutbolt40
+    ref = run_backward(b, pose, per_env=False)
+    ref_env = run_backward(b, pose, per_env=True)
+    old = b.get_launch()
+    try:
+        b.set_launch(**dict(old, xcd_remap=1))
+        assert_same(run_backward(b, pose, per_env=False), ref)
+        assert_same(run_backward(b, pose, per_env=True), ref_env)
+    finally:
+        b.set_launch(**old)
+    bo = fc.Batch.from_workload(w, env_order=np.arange(w.n_env)[::-1].copy())
+    r = run_backward(bo, pose, per_env=False)
+    assert_same(dict(l=r["loss"], p=r["d_pose"]), dict(l=ref["loss"], p=ref["d_pose"]))
+    assert np.allclose(r["d_verts"], ref["d_verts"], rtol=1e-5, atol=1e-6 * np.abs(ref["d_verts"]).max())
+
+
 def test_upstream_scaling(torus16):
     torch = torch_gpu()
     w, b, pose = torus16

@@ -100,6 +100,10 @@ def test_nutbolt_candidates_and_reduction(nutbolt24):
     dict(block=512, tile=2048, persistent=2, grid_mult=4),
     dict(block=128, tile=512, persistent=2, grid_mult=1),
     dict(block=256, tile=256, persistent=1, grid_mult=32),
+    dict(block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=1),
+    dict(block=256, tile=1024, persistent=1, grid_mult=4, xcd_remap=1),
+    dict(block=256, tile=1024, persistent=2, grid_mult=8, xcd_remap=1),
+    dict(block=512, tile=512, persistent=2, grid_mult=1, xcd_remap=1),
 ])
 def test_launch_shapes_bit_identical(nutbolt24, shape):
     w, b, pose = nutbolt24
@@ -113,6 +117,17 @@ def test_launch_shapes_bit_identical(nutbolt24, shape):
             assert_same(o, ref_o)
     finally:
         b.set_launch(**old)
+
+
+def test_env_order_does_not_change_contacts(nutbolt24):
+    w, b, pose = nutbolt24
+    ref_c, ref_o = run(b, pose)
+    for order in (fc.locality_order(w), np.arange(w.n_env)[::-1].copy()):
+        bo = fc.Batch.from_workload(w, env_order=order)
+        bo.set_launch(block=256, tile=1024, persistent=2, grid_mult=8, xcd_remap=1)
+        c, o = run(bo, pose)
+        assert_same(c, ref_c)
+        assert_same(o, ref_o)
 
 
 def test_brick_layout_bit_identical(nutbolt24):
