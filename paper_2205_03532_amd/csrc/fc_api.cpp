@@ -140,6 +140,76 @@ fc_status upload(T** dst, const std::vector<T>& v) {
   return FC_OK;
 }
 
+// --- normal-bin search table ------------------------------------------------
+// For each cube-map cell: every bin k that can be the argmax of n.d_k for some
+// unit normal n in the cell.  The cell lies in the cone around its centre c
+// whose half-angle alpha reaches its farthest corner (plus a margin for the
+// FP32 cell choice); over that cone n.d_k <= |d_k| cos(max(theta_k - alpha, 0))
+// and max_j n.d_j >= max_j |d_j| cos(min(theta_j + alpha, pi)), theta = the
+// angle to c.  Bins whose upper bound falls short of the best lower bound by
+// more than the FP32 dot-product error can never win; the rest are listed.
+std::vector<BinCell> build_bin_lut(const std::vector<float>& dirs, int K) {
+  const double kPi = 3.14159265358979323846;
+  auto face_dir = [](int f, double u, double v, double out[3]) {
+    switch (f) {
+      case 0: out[0] = 1; out[1] = u; out[2] = v; break;
+      case 1: out[0] = -1; out[1] = u; out[2] = v; break;
+      case 2: out[0] = u; out[1] = 1; out[2] = v; break;
+      case 3: out[0] = u; out[1] = -1; out[2] = v; break;
+      case 4: out[0] = u; out[1] = v; out[2] = 1; break;
+      default: out[0] = u; out[1] = v; out[2] = -1; break;
+    }
+    const double n = std::sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
+    for (int a = 0; a < 3; ++a) out[a] /= n;
+  };
+  std::vector<double> dk(3 * K), dn(K);
+  for (int k = 0; k < K; ++k) {
+    for (int a = 0; a < 3; ++a) dk[3 * k + a] = dirs[a * K + k];
+    dn[k] = std::sqrt(dk[3 * k] * dk[3 * k] + dk[3 * k + 1] * dk[3 * k + 1] + dk[3 * k + 2] * dk[3 * k + 2]);
+  }
+  std::vector<BinCell> lut(kLutCells);
+  for (int f = 0; f < 6; ++f)
+    for (int iv = 0; iv < kLutN; ++iv)
+      for (int iu = 0; iu < kLutN; ++iu) {
+        BinCell& cell = lut[(f * kLutN + iv) * kLutN + iu];
+        std::memset(&cell, 0, sizeof(cell));
+        double c[3], q[3];
+        face_dir(f, -1.0 + 2.0 * (iu + 0.5) / kLutN, -1.0 + 2.0 * (iv + 0.5) / kLutN, c);
+        double alpha = 0;
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) {
+            face_dir(f, -1.0 + 2.0 * (iu + a) / kLutN, -1.0 + 2.0 * (iv + b) / kLutN, q);
+            const double dot = std::min(1.0, c[0] * q[0] + c[1] * q[1] + c[2] * q[2]);
+            alpha = std::max(alpha, std::acos(dot));
+          }
+        alpha += 1e-4;
+        std::vector<double> up(K), lo(K);
+        double best_lo = -1e30;
+        for (int k = 0; k < K; ++k) {
+          double th = 0.5 * kPi;
+          if (dn[k] > 0) {
+            const double cs = (c[0] * dk[3 * k] + c[1] * dk[3 * k + 1] + c[2] * dk[3 * k + 2]) / dn[k];
+            th = std::acos(std::max(-1.0, std::min(1.0, cs)));
+          }
+          up[k] = dn[k] * std::cos(std::max(th - alpha, 0.0));
+          lo[k] = dn[k] * std::cos(std::min(th + alpha, kPi));
+          best_lo = std::max(best_lo, lo[k]);
+        }
+        int n = 0;
+        bool full = false;
+        for (int k = 0; k < K; ++k) {
+          if (up[k] < best_lo - 1e-5) continue;
+          if (n == kLutMax) {
+            full = true;
+            break;
+          }
+          cell.k[n++] = (unsigned char)k;
+        }
+        cell.n = full ? kLutFull : (unsigned char)n;
+      }
+  return lut;
+}
+
 // --- a small JSON reader for the autotune cache -----------------------------
 struct JVal {
   enum Kind { NUL, NUM, STR, ARR, OBJ, BOOL } kind = NUL;
@@ -280,6 +350,7 @@ struct fc_batch {
   int num_cus = 256;
   std::string signature;
   // forward tables
+  BinCell* d_lut = nullptr;
   Item* d_items = nullptr;
   int n_items = 0;
   EnvInfo* d_envs = nullptr;
@@ -302,6 +373,8 @@ struct fc_batch {
 namespace {
 
 void free_tables(fc_batch* b) {
+  if (b->d_lut) (void)hipFree(b->d_lut);
+  b->d_lut = nullptr;
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_envs) (void)hipFree(b->d_envs);
   if (b->d_bitems) (void)hipFree(b->d_bitems);
@@ -420,7 +493,7 @@ fc_status build_backward_tables(fc_batch* b) {
   b->off_workctr = off;
   off = align256(off + kXcds * 4);
   b->off_pose = off;
-  off = align256(off + (size_t)rows * 8 * sizeof(float2));
+  off = align256(off + (size_t)rows * (kBwdBlock / 64) * 8 * sizeof(float2));
   b->off_vert = off;
   off = align256(off + (size_t)vpart * sizeof(float2));
   b->ws_bytes = off;
@@ -459,6 +532,7 @@ FwdArgs make_fwd(const fc_batch* b, const float* pose, const fc_candidates* cand
   std::memset(&a, 0, sizeof(a));
   fill_common(b, a.grids, a.meshes);
   for (int i = 0; i < 3 * b->K; ++i) a.dirs[i] = b->dirs[i];
+  a.bin_lut = b->d_lut;
   a.items = b->d_items;
   a.envs = b->d_envs;
   a.pose = pose;
@@ -617,7 +691,8 @@ fc_status fc_batch_create(const fc_batch_desc* desc, fc_batch** out) {
     auto it = g_tune.find(b->signature);
     if (it != g_tune.end() && launch_valid(it->second)) b->launch = it->second;
   }
-  s = build_forward_tables(b);
+  s = upload(&b->d_lut, build_bin_lut(b->dirs, b->K));
+  if (s == FC_OK) s = build_forward_tables(b);
   if (s == FC_OK) s = build_backward_tables(b);
   if (s != FC_OK) {
     free_tables(b);

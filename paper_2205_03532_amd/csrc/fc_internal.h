@@ -23,6 +23,18 @@ constexpr int kXcds = 8;
 constexpr int kBrickCells = 3;
 constexpr int kBrickNodes = 4;
 
+// Normal-bin search table: a cube map of 6 x kLutN x kLutN cells over the
+// unit sphere; each cell lists (ascending) every bin that can be the argmax
+// for a normal in that cell, or is marked for a full search.
+constexpr int kLutN = 8;
+constexpr int kLutCells = 6 * kLutN * kLutN;
+constexpr int kLutMax = 15;
+constexpr unsigned char kLutFull = 0xFF;
+struct BinCell {
+  unsigned char n;  // number of candidate bins, or kLutFull
+  unsigned char k[kLutMax];
+};
+
 struct GridDev {
   const void* data;
   int nx, ny, nz;
@@ -56,6 +68,7 @@ struct FwdArgs {
   GridDev grids[FC_MAX_TYPES];
   MeshDev meshes[FC_MAX_TYPES];
   float dirs[3 * FC_MAX_BINS];  // [3][K]
+  const BinCell* bin_lut;       // [kLutCells]
   const Item* items;
   const EnvInfo* envs;
   const float* pose;  // [7][n_env]
@@ -123,7 +136,7 @@ struct BwdArgs {
   float* d_pose;
   float* d_verts;
   // workspace: partial sums, fully overwritten by every call
-  float2* pose_part;  // [rows][8]: 7 used
+  float2* pose_part;  // [(env, tile) rows][waves][8]: 7 used
   float2* vert_part;  // per chunk [3][n_v]
 };
 

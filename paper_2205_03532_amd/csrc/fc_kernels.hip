@@ -200,6 +200,59 @@ __device__ __forceinline__ int argmax_bin(const float* __restrict__ dirs, int K,
   return bin;
 }
 
+// Cube-map cell of a nonzero normal (see BinCell): the dominant axis picks the
+// face, the other two components divided by it give (u, v) in [-1, 1].
+__device__ __forceinline__ int cube_cell(float nx, float ny, float nz) {
+  const float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
+  int face;
+  float u, v, m;
+  if ((ax >= ay) & (ax >= az)) {
+    face = nx >= 0.f ? 0 : 1;
+    u = ny;
+    v = nz;
+    m = ax;
+  } else if (ay >= az) {
+    face = ny >= 0.f ? 2 : 3;
+    u = nx;
+    v = nz;
+    m = ay;
+  } else {
+    face = nz >= 0.f ? 4 : 5;
+    u = nx;
+    v = ny;
+    m = az;
+  }
+  const float s = (0.5f * kLutN) / m;
+  const int iu = min(max((int)floorf(fmaf(u, s, 0.5f * kLutN)), 0), kLutN - 1);
+  const int iv = min(max((int)floorf(fmaf(v, s, 0.5f * kLutN)), 0), kLutN - 1);
+  return (face * kLutN + iv) * kLutN + iu;
+}
+
+// The same argmax as argmax_bin (same dot products, same lowest-k tie rule),
+// evaluated only over the bins the normal's cube-map cell lists.  The table
+// is built so that every bin that can reach the maximum for a normal in the
+// cell is listed, so the result is identical.
+__device__ __forceinline__ int argmax_bin_lut(const BinCell* __restrict__ lut, const float4* __restrict__ dir4,
+                                              const float* __restrict__ dirs, int K, float nx, float ny,
+                                              float nz) {
+  if ((nx == 0.f) & (ny == 0.f) & (nz == 0.f)) return 0;
+  const BinCell c = lut[cube_cell(nx, ny, nz)];
+  if (c.n == kLutFull) return argmax_bin(dirs, K, nx, ny, nz);
+  int bin = c.k[0];
+  float4 d = dir4[bin];
+  float best = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
+  for (int i = 1; i < c.n; ++i) {
+    const int k = c.k[i];
+    d = dir4[k];
+    const float v = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
+    if (v > best) {
+      best = v;
+      bin = k;
+    }
+  }
+  return bin;
+}
+
 // ---------------------------------------------------------------------------
 // reduction keys: (sortable depth << 32) | (0xFFFFFFFF - vidx); max = deepest,
 // then lowest index.  -0.0 is folded to +0.0; key 0 means "empty".
@@ -219,26 +272,62 @@ __device__ __forceinline__ float key_depth(unsigned long long key) {
 
 __device__ __forceinline__ unsigned key_vidx(unsigned long long key) { return 0xFFFFFFFFu - (unsigned)key; }
 
+// ---------------------------------------------------------------------------
+// wavefront reductions with DPP row permutations (register-to-register, no
+// LDS traffic): xor-1 and xor-2 quad permutes, then the half-row and row
+// mirrors complete each 16-lane row; the four row results are read with
+// readlane and combined in row order.  Needs all 64 lanes active.
+// ---------------------------------------------------------------------------
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <- lane 7-i within each 8 lanes
+constexpr int kDppMirror = 0x140;     // lane i <- lane 15-i within each row
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u(unsigned v) {
+  return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_max64(unsigned long long v) {
+  const unsigned lo = dpp_u<CTRL>((unsigned)v), hi = dpp_u<CTRL>((unsigned)(v >> 32));
+  return umax64(v, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// max over all 64 lanes; the result is wave-uniform
+__device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
+  v = dpp_max64<kDppXor1>(v);
+  v = dpp_max64<kDppXor2>(v);
+  v = dpp_max64<kDppHalfMirror>(v);
+  v = dpp_max64<kDppMirror>(v);
+  return umax64(umax64(readlane64(v, 0), readlane64(v, 16)), umax64(readlane64(v, 32), readlane64(v, 48)));
+}
+
 // Per-bin max over the candidate lanes of a wavefront: one iteration per
-// distinct bin present (ballot picks the bin, a butterfly of shuffles takes
-// the 64-bit max), then one LDS atomicMax by the bin's leader lane.
+// distinct bin present (ballot picks the bin, a DPP reduction takes the
+// 64-bit max), then one LDS atomicMax by the bin's leader lane.
 __device__ __forceinline__ void wave_bin_max(bool cand, int bin, unsigned long long key,
                                              unsigned long long* s_keys) {
   unsigned long long active = __ballot(cand);
   const int lane = __lane_id();
   while (active) {
     const int leader = __ffsll((long long)active) - 1;
-    const int lb = __shfl(bin, leader);
+    const int lb = __builtin_amdgcn_readlane(bin, leader);
     const bool mine = cand && (bin == lb);
     const unsigned long long m = __ballot(mine);
     unsigned long long v = mine ? key : 0ull;
-    if (__popcll(m) > 1) {
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(v, off);
-        v = o > v ? o : v;
-      }
-    }
+    if (__popcll(m) > 1) v = wave_max64(v);
     if (lane == leader) atomicMax(&s_keys[lb], v);
     active &= ~m;
   }
@@ -248,7 +337,8 @@ __device__ __forceinline__ void wave_bin_max(bool cand, int bin, unsigned long l
 // forward: one work item = up to BLOCK*VPT vertices of one environment
 // ---------------------------------------------------------------------------
 template <int DT, int LAYOUT, int BLOCK, int VPT>
-__device__ __forceinline__ void query_item(const FwdArgs& A, const Item& it, unsigned long long* s_keys, bool fused) {
+__device__ __forceinline__ void query_item(const FwdArgs& A, const Item& it, unsigned long long* s_keys, bool fused,
+                                           const BinCell* s_lut, const float4* s_dir4) {
   const GridDev& g = A.grids[it.gm & 0xff];
   const MeshDev& m = A.meshes[it.gm >> 8];
   const Rigid P = load_pose(A.pose, A.n_env, it.env);
@@ -287,7 +377,7 @@ __device__ __forceinline__ void query_item(const FwdArgs& A, const Item& it, uns
     float nx = 0.f, ny = 0.f, nz = 0.f;
     int bin = -1;
     if (cand | (want_cand & inside)) normalize(gx, gy, gz, nx, ny, nz);
-    if (cand) bin = argmax_bin(A.dirs, A.K, nx, ny, nz);
+    if (cand) bin = argmax_bin_lut(s_lut, s_dir4, A.dirs, A.K, nx, ny, nz);
     const int v = it.vstart + j * BLOCK + tid;
     if (want_cand & ok[j]) {
       const long long q = qoff + v;
@@ -420,8 +510,21 @@ template <int DT, int LAYOUT, int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_forward(FwdArgs A, int persistent, int from_cand, int xcd) {
   __shared__ unsigned long long s_keys[FC_MAX_BINS];
   __shared__ int s_item;
+  __shared__ BinCell s_lut[kLutCells];
+  __shared__ float4 s_dir4[FC_MAX_BINS];
   const bool fused = A.o_vidx != nullptr;
   const ItemRange R = item_range(A.n_items, xcd, A.work_ctr);
+  if (!from_cand) {  // bin-search tables into LDS
+    static_assert(sizeof(BinCell) == sizeof(uint4), "BinCell is one 16-byte load");
+    const uint4* src = reinterpret_cast<const uint4*>(A.bin_lut);
+    uint4* dst = reinterpret_cast<uint4*>(s_lut);
+    for (int i = threadIdx.x; i < kLutCells; i += BLOCK) dst[i] = src[i];
+    if (threadIdx.x < FC_MAX_BINS) {
+      const int k = threadIdx.x < A.K ? threadIdx.x : 0;
+      s_dir4[threadIdx.x] = make_float4(A.dirs[k], A.dirs[A.K + k], A.dirs[2 * A.K + k], 0.f);
+    }
+    __syncthreads();
+  }
   int idx;
   if (persistent == 2) {
     if (threadIdx.x == 0) s_item = R.lo + (int)atomicAdd(R.ctr, 1u);
@@ -440,7 +543,7 @@ __global__ __launch_bounds__(BLOCK) void k_forward(FwdArgs A, int persistent, in
     if (from_cand)
       reduce_item<BLOCK, VPT>(A, it, s_keys);
     else
-      query_item<DT, LAYOUT, BLOCK, VPT>(A, it, s_keys, fused);
+      query_item<DT, LAYOUT, BLOCK, VPT>(A, it, s_keys, fused, s_lut, s_dir4);
     if (fused) {
       __syncthreads();
       item_flush(A, it, s_keys);
@@ -493,11 +596,32 @@ __device__ __forceinline__ float2 ncombine(float2 a, float2 b) {
   return make_float2(t, (a.y + b.y) + e);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float2 dpp_pair(float2 a) {
+  return make_float2(dpp_f<CTRL>(a.x), dpp_f<CTRL>(a.y));
+}
+__device__ __forceinline__ float2 readlane_pair(float2 a, int lane) {
+  return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.x), lane)),
+                     __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.y), lane)));
+}
+
+// Compensated sum of a (sum, compensation) pair over the 64 lanes, in a fixed
+// order (quad, half-row, row, then rows 0..3); wave-uniform result.
+__device__ __forceinline__ float2 wave_sum_pair(float2 a) {
+  a = ncombine(a, dpp_pair<kDppXor1>(a));
+  a = ncombine(a, dpp_pair<kDppXor2>(a));
+  a = ncombine(a, dpp_pair<kDppHalfMirror>(a));
+  a = ncombine(a, dpp_pair<kDppMirror>(a));
+  float2 r = readlane_pair(a, 0);
+  r = ncombine(r, readlane_pair(a, 16));
+  r = ncombine(r, readlane_pair(a, 32));
+  return ncombine(r, readlane_pair(a, 48));
+}
+
 template <int DT, int LAYOUT>
 __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
   constexpr int V = kBwdTile / kBwdBlock;
   constexpr int NW = kBwdBlock / 64;
-  __shared__ float2 s_red[NW][8];
   int idx = blockIdx.x;
   if (A.xcd) {  // XCD x serves the x-th contiguous range of items (see item_range)
     const int per = (A.n_items + kXcds - 1) / kXcds;
@@ -582,31 +706,23 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
         A.d_verts[2 * A.Q + q] = dvz;
       }
     }
-    // fixed-shape reduction: butterfly within each wave, then waves in order
+    // fixed-shape reduction within the wavefront (DPP rows, then rows in
+    // order); one partial row per (env, tile, wave), no workgroup barrier
+    float2 red[7];
     if (__ballot(any) != 0ull) {
 #pragma unroll
-      for (int i = 0; i < 7; ++i) {
+      for (int i = 0; i < 7; ++i) red[i] = wave_sum_pair(acc[i]);
+    } else {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          float2 o;
-          o.x = __shfl_xor(acc[i].x, off);
-          o.y = __shfl_xor(acc[i].y, off);
-          acc[i] = ncombine(acc[i], o);
-        }
-      }
+      for (int i = 0; i < 7; ++i) red[i] = make_float2(0.f, 0.f);
     }
-    if (lane == 0) {
+    if (lane < 7) {
+      float2 r = red[0];
 #pragma unroll
-      for (int i = 0; i < 7; ++i) s_red[wave][i] = acc[i];
+      for (int i = 1; i < 7; ++i)
+        if (lane == i) r = red[i];
+      A.pose_part[((long long)(A.env_tile_base[e] + it.tile_in_mesh) * NW + wave) * 8 + lane] = r;
     }
-    __syncthreads();
-    if (tid < 7) {
-      float2 r = s_red[0][tid];
-#pragma unroll
-      for (int w = 1; w < NW; ++w) r = ncombine(r, s_red[w][tid]);
-      A.pose_part[(long long)(A.env_tile_base[e] + it.tile_in_mesh) * 8 + tid] = r;
-    }
-    __syncthreads();
   }
 
   if (shared_v) {
@@ -635,10 +751,11 @@ __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, lo
   if (i < n_pose) {
     const int e = (int)(i / 7);
     const int val = (int)(i - (long long)e * 7);
-    const int n_tiles = A.mesh_tiles[A.envs[e].gm >> 8];
-    const float2* part = A.pose_part + (long long)A.env_tile_base[e] * 8 + val;
+    constexpr int NW = kBwdBlock / 64;
+    const int n_rows = A.mesh_tiles[A.envs[e].gm >> 8] * NW;  // (tile, wave) rows in order
+    const float2* part = A.pose_part + (long long)A.env_tile_base[e] * NW * 8 + val;
     float2 r = part[0];
-    for (int t = 1; t < n_tiles; ++t) r = ncombine(r, part[(long long)t * 8]);
+    for (int t = 1; t < n_rows; ++t) r = ncombine(r, part[(long long)t * 8]);
     const float v = r.x + r.y;
     if (val == 0) {
       if (A.loss) A.loss[e] = v;

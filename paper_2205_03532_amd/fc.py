@@ -336,8 +336,9 @@ def locality_order(w):
     consecutive envs sit near each other in B's frame.  Host-side, from the
     poses the caller already has."""
     t = np.asarray(w.pose[4:7], dtype=np.float64).T
-    lo, hi = t.min(axis=0), t.max(axis=0)
-    span = np.where(hi > lo, hi - lo, 1.0)
+    lo = t.min(axis=0)
+    span = float(np.max(t.max(axis=0) - lo))  # one scale for all axes: the curve follows the real extent
+    span = span if span > 0 else 1.0
     q = np.clip(((t - lo) / span * 1023).astype(np.int64), 0, 1023)
     code = np.zeros(len(t), dtype=np.int64)
     for bit in range(10):

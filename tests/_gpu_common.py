@@ -52,6 +52,74 @@ def gradient_sensitivity(w, o):
     return S, cmax
 
 
+def _round_fraction_f32(x):
+    """Round an exact rational to float32, nearest-even."""
+    from fractions import Fraction
+
+    r0 = np.float32(float(x))
+    cands = [r0, np.nextafter(r0, np.float32(np.inf)), np.nextafter(r0, np.float32(-np.inf))]
+    best = None
+    for c in cands:
+        d = abs(Fraction(float(c)) - x)
+        even = (int(np.asarray(c, np.float32).view(np.uint32)) & 1) == 0
+        key = (d, 0 if even else 1)
+        if best is None or key < best[0]:
+            best = (key, c)
+    return best[1]
+
+
+def fma32(a, b, c):
+    """float32 fma(a, b, c) with a single rounding, exactly.
+
+    a*b is exact in float64 (24 x 24 bits); a*b + c is rounded once to float64
+    and then to float32.  That double rounding can only differ from the single
+    rounding when the float64 sum lies within a few float64 ulps of a float32
+    midpoint; those elements are redone in exact rational arithmetic."""
+    from fractions import Fraction
+
+    a64, b64, c64 = (np.asarray(x, np.float32).astype(np.float64) for x in (a, b, c))
+    s = a64 * b64 + c64
+    r = s.astype(np.float32)
+    r64 = r.astype(np.float64)
+    up = np.nextafter(r, np.float32(np.inf)).astype(np.float64)
+    dn = np.nextafter(r, np.float32(-np.inf)).astype(np.float64)
+    d = np.minimum(np.abs(s - (r64 + up) / 2), np.abs(s - (r64 + dn) / 2))
+    risky = np.nonzero(d <= 4 * np.spacing(np.abs(s)))[0]
+    for i in risky:
+        r[i] = _round_fraction_f32(Fraction(float(a64[i])) * Fraction(float(b64[i])) + Fraction(float(c64[i])))
+    return r
+
+
+def bins_fp32(normal, dirs):
+    """The kernels' bin rule on given float32 normals: d_k = fma(nz, dz, fma(ny, dy, nx*dx)),
+    lowest k with the largest d_k (strict >), evaluated exactly in float32."""
+    nx, ny, nz = (np.asarray(v, np.float32) for v in normal)
+    D = np.asarray(dirs, np.float32)
+    K = D.shape[1]
+    best = fma32(nz, D[2, 0], fma32(ny, D[1, 0], nx * D[0, 0]))
+    b = np.zeros(len(nx), np.int64)
+    for k in range(1, K):
+        v = fma32(nz, D[2, k], fma32(ny, D[1, k], nx * D[0, k]))
+        better = v > best
+        best = np.where(better, v, best)
+        b = np.where(better, k, b)
+    return b
+
+
+def check_bins_exact(w, cand, envs):
+    """Every candidate's bin equals the kernels' rule re-evaluated on the CPU
+    from the GPU's own normal (bit-exact: catches any omission in the bin
+    search table)."""
+    rows = rows_of(w, envs)
+    b = cand["bin"][rows].astype(np.int64)
+    sel = np.nonzero(b >= 0)[0]
+    nrm = cand["normal"][:, rows[sel]]
+    ref = bins_fp32(nrm, w.bins)
+    bad = ref != b[sel]
+    assert not bad.any(), f"bin differs from the FP32 rule at rows {rows[sel][bad][:10]}"
+    return int(len(sel))
+
+
 def torch_gpu():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
@@ -181,6 +249,7 @@ def check_candidates(w, cand, envs, depth_tol=DEPTH_TOL_F32, o=None):
     bad = cc & ~okb
     assert not bad.any(), f"bin mismatch at rows {rows[bad][:10]}"
     stats["bin_near_tie"] = int((cc & (b != o["bin"])).sum())
+    stats["bins_checked_exact"] = check_bins_exact(w, cand, envs)
     stats["n"] = int(len(rows))
     stats["cand"] = int(g_cand.sum())
     return stats
