@@ -104,7 +104,7 @@ def main():
     ap.add_argument("--n-env", type=int, default=1000)
     ap.add_argument("--layout", default=None, choices=[None, "linear", "brick"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--cpu-sample", type=int, default=400)
+    ap.add_argument("--cpu-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates rocprof byte counters) and exit")

@@ -63,9 +63,14 @@ typedef enum fc_dtype { FC_F32 = 0, FC_F16 = 1, FC_BF16 = 2 } fc_dtype;
 /* FC_LAYOUT_LINEAR: samples [nz][ny][nx], x fastest.
  * FC_LAYOUT_BRICK:  the same samples re-laid out by fc_grid_to_bricks into
  *                   bricks of 4x4x4 nodes covering 3x3x3 cells (neighbouring
- *                   bricks share their face nodes), so the 8 corners of any
- *                   cell lie in one brick.  Values are copied, not rounded. */
-typedef enum fc_layout { FC_LAYOUT_LINEAR = 0, FC_LAYOUT_BRICK = 1 } fc_layout;
+ *                   bricks duplicate their shared face nodes), so the 8
+ *                   corners of any cell lie in one brick (FP32: 256 bytes,
+ *                   FP16/BF16: one 128-byte line).
+ * FC_LAYOUT_SLAB:   bricks of 4x4x2 nodes covering 3x3x1 cells (FP32: one
+ *                   128-byte line per cell lookup).
+ * Bricks are stored z-major, then y, then x; inside a brick x is fastest.
+ * Values are copied, not rounded. */
+typedef enum fc_layout { FC_LAYOUT_LINEAR = 0, FC_LAYOUT_BRICK = 1, FC_LAYOUT_SLAB = 2 } fc_layout;
 
 #define FC_MAX_TYPES 8 /* distinct grids and distinct meshes per batch */
 #define FC_MAX_BINS 64 /* normal bins K */
@@ -250,13 +255,15 @@ void fc_graph_destroy(fc_graph* graph);
 
 /* ---- layout conversion -------------------------------------------------- */
 
-/* Bytes of the brick layout of `src` (same dtype); 0 on invalid input. */
-size_t fc_grid_brick_bytes(const fc_grid* src);
+/* Bytes of `src` (a linear grid) re-laid out as `layout` (FC_LAYOUT_BRICK or
+ * FC_LAYOUT_SLAB), same dtype; 0 on invalid input. */
+size_t fc_grid_brick_bytes(const fc_grid* src, int32_t layout);
 
-/* Re-lay out a linear grid into bricks: writes dst_data (device,
+/* Re-lay out a linear grid as `layout`: writes dst_data (device,
  * fc_grid_brick_bytes bytes) and fills *dst with a descriptor of the result.
- * Exact copy of the values (no rounding). */
-fc_status fc_grid_to_bricks(const fc_grid* src, void* dst_data, size_t dst_bytes, fc_grid* dst, void* stream);
+ * Exact copy of the values (no rounding).  Asynchronous on stream. */
+fc_status fc_grid_to_bricks(const fc_grid* src, int32_t layout, void* dst_data, size_t dst_bytes, fc_grid* dst,
+                            void* stream);
 
 /* ---- autotuning and diagnostics ----------------------------------------- */
 

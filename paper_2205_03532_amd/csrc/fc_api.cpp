@@ -41,24 +41,30 @@ bool finitef(float x) { return std::isfinite(x); }
 
 int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-void bricks_of(const fc_grid& g, int& bx, int& by, int& bz) {
-  bx = ceil_div(g.nx - 1, kBrickCells);
-  by = ceil_div(g.ny - 1, kBrickCells);
-  bz = ceil_div(g.nz - 1, kBrickCells);
+// bricks per axis of grid g stored (or to be stored) as `layout`
+void bricks_of(const fc_grid& g, int layout, int& bx, int& by, int& bz) {
+  int nx, ny, nz;
+  brick_nodes(layout, nx, ny, nz);
+  bx = ceil_div(g.nx - 1, nx - 1);
+  by = ceil_div(g.ny - 1, ny - 1);
+  bz = ceil_div(g.nz - 1, nz - 1);
 }
+
+bool is_brick(int layout) { return layout == FC_LAYOUT_BRICK || layout == FC_LAYOUT_SLAB; }
 
 int elem_size(int dtype) { return dtype == FC_F32 ? 4 : 2; }
 
 fc_status check_grid(const fc_grid& g) {
   if (!g.data) return FC_ERR_NULL;
   if (g.dtype < FC_F32 || g.dtype > FC_BF16) return FC_ERR_DTYPE;
-  if (g.layout != FC_LAYOUT_LINEAR && g.layout != FC_LAYOUT_BRICK) return FC_ERR_DTYPE;
+  if (g.layout != FC_LAYOUT_LINEAR && !is_brick(g.layout)) return FC_ERR_DTYPE;
   if (g.nx < 2 || g.ny < 2 || g.nz < 2) return FC_ERR_SHAPE;
   if ((long long)g.nx * g.ny * g.nz >= (1LL << 31)) return FC_ERR_SHAPE;
-  if (g.layout == FC_LAYOUT_BRICK) {
-    int bx, by, bz;
-    bricks_of(g, bx, by, bz);
-    if ((long long)bx * by * bz * 64 >= (1LL << 31)) return FC_ERR_SHAPE;
+  if (is_brick(g.layout)) {
+    int bx, by, bz, nx, ny, nz;
+    bricks_of(g, g.layout, bx, by, bz);
+    brick_nodes(g.layout, nx, ny, nz);
+    if ((long long)bx * by * bz * nx * ny * nz >= (1LL << 31)) return FC_ERR_SHAPE;
   }
   if (!(g.h > 0.f) || !finitef(g.h) || !finitef(1.f / g.h)) return FC_ERR_RANGE;
   for (int a = 0; a < 3; ++a)
@@ -120,8 +126,8 @@ GridDev to_dev(const fc_grid& g) {
   d.nx = g.nx;
   d.ny = g.ny;
   d.nz = g.nz;
-  int bx, by, bz;
-  bricks_of(g, bx, by, bz);
+  int bx = 0, by = 0, bz = 0;
+  if (is_brick(g.layout)) bricks_of(g, g.layout, bx, by, bz);
   d.bx = bx;
   d.by = by;
   d.ox = g.origin[0];
@@ -833,32 +839,35 @@ void fc_graph_destroy(fc_graph* g) {
   delete g;
 }
 
-size_t fc_grid_brick_bytes(const fc_grid* src) {
-  if (!src) return 0;
+size_t fc_grid_brick_bytes(const fc_grid* src, int32_t layout) {
+  if (!src || !is_brick(layout)) return 0;
   fc_grid g = *src;
-  g.layout = FC_LAYOUT_BRICK;
+  g.layout = layout;
   if (!g.data) g.data = (const void*)1;  // size query only
   if (check_grid(g) != FC_OK) return 0;
-  int bx, by, bz;
-  bricks_of(g, bx, by, bz);
-  return (size_t)bx * by * bz * kBrickNodes * kBrickNodes * kBrickNodes * elem_size(g.dtype);
+  int bx, by, bz, nx, ny, nz;
+  bricks_of(g, layout, bx, by, bz);
+  brick_nodes(layout, nx, ny, nz);
+  return (size_t)bx * by * bz * nx * ny * nz * elem_size(g.dtype);
 }
 
-fc_status fc_grid_to_bricks(const fc_grid* src, void* dst_data, size_t dst_bytes, fc_grid* dst, void* stream) {
+fc_status fc_grid_to_bricks(const fc_grid* src, int32_t layout, void* dst_data, size_t dst_bytes, fc_grid* dst,
+                            void* stream) {
   if (!src || !dst_data || !dst) return FC_ERR_NULL;
+  if (!is_brick(layout)) return FC_ERR_DTYPE;
   fc_status s = check_grid(*src);
   if (s != FC_OK) return s;
   if (src->layout != FC_LAYOUT_LINEAR) return FC_ERR_DTYPE;
-  const size_t need = fc_grid_brick_bytes(src);
+  const size_t need = fc_grid_brick_bytes(src, layout);
   if (need == 0) return FC_ERR_SHAPE;
   if (dst_bytes < need) return FC_ERR_WORKSPACE;
   int bx, by, bz;
-  bricks_of(*src, bx, by, bz);
-  FC_HIP(launch_to_bricks(src->data, dst_data, elem_size(src->dtype), src->nx, src->ny, src->nz, bx, by, bz,
+  bricks_of(*src, layout, bx, by, bz);
+  FC_HIP(launch_to_bricks(src->data, dst_data, elem_size(src->dtype), layout, src->nx, src->ny, src->nz, bx, by, bz,
                           (hipStream_t)stream));
   *dst = *src;
   dst->data = dst_data;
-  dst->layout = FC_LAYOUT_BRICK;
+  dst->layout = layout;
   return FC_OK;
 }
 

@@ -19,9 +19,24 @@ constexpr int kBwdChunk = 32;   // environments per backward item (vertex partia
 // Dispatch places workgroup i on XCD i mod kXcds (MI355X: 8 XCDs, one L2 each).
 constexpr int kXcds = 8;
 
-// Brick layout: 4x4x4 nodes per brick covering 3x3x3 cells.
-constexpr int kBrickCells = 3;
-constexpr int kBrickNodes = 4;
+// Brick layouts: nodes per brick along x, y, z (cells per brick = nodes - 1).
+template <int LAYOUT>
+struct BrickShape;
+template <>
+struct BrickShape<FC_LAYOUT_BRICK> {
+  static constexpr int NX = 4, NY = 4, NZ = 4;
+};
+template <>
+struct BrickShape<FC_LAYOUT_SLAB> {
+  static constexpr int NX = 4, NY = 4, NZ = 2;
+};
+inline void brick_nodes(int layout, int& nx, int& ny, int& nz) {
+  if (layout == FC_LAYOUT_SLAB) {
+    nx = BrickShape<FC_LAYOUT_SLAB>::NX, ny = BrickShape<FC_LAYOUT_SLAB>::NY, nz = BrickShape<FC_LAYOUT_SLAB>::NZ;
+  } else {
+    nx = BrickShape<FC_LAYOUT_BRICK>::NX, ny = BrickShape<FC_LAYOUT_BRICK>::NY, nz = BrickShape<FC_LAYOUT_BRICK>::NZ;
+  }
+}
 
 // Normal-bin search table: a cube map of 6 x kLutN x kLutN cells over the
 // unit sphere; each cell lists (ascending) every bin that can be the argmax
@@ -145,8 +160,8 @@ hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, in
                           int grid, bool from_cand, hipStream_t s);
 hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
-hipError_t launch_to_bricks(const void* src, void* dst, int elem, int nx, int ny, int nz, int bx, int by, int bz,
-                            hipStream_t s);
+hipError_t launch_to_bricks(const void* src, void* dst, int elem, int layout, int nx, int ny, int nz, int bx, int by,
+                            int bz, hipStream_t s);
 bool forward_shape_supported(int block, int vpt);
 
 }  // namespace fcimpl

@@ -122,16 +122,18 @@ __device__ __forceinline__ float2 ld_pair<kBF16>(const void* __restrict__ base, 
 template <int DT, int LAYOUT>
 __device__ __forceinline__ void gather(const GridDev& g, const Cell& cl, float c[8]) {
   int i0, sy, sz;
-  if (LAYOUT == FC_LAYOUT_LINEAR) {
+  if constexpr (LAYOUT == FC_LAYOUT_LINEAR) {
     sy = g.nx;
     sz = g.nx * g.ny;
     i0 = (cl.iz * g.ny + cl.iy) * g.nx + cl.ix;
   } else {
-    const int bxi = cl.ix / kBrickCells, byi = cl.iy / kBrickCells, bzi = cl.iz / kBrickCells;
-    const int lx = cl.ix - kBrickCells * bxi, ly = cl.iy - kBrickCells * byi, lz = cl.iz - kBrickCells * bzi;
-    sy = kBrickNodes;
-    sz = kBrickNodes * kBrickNodes;
-    i0 = ((bzi * g.by + byi) * g.bx + bxi) * (kBrickNodes * kBrickNodes * kBrickNodes) + (lz * sz + ly * sy + lx);
+    using B = BrickShape<LAYOUT>;
+    constexpr int CX = B::NX - 1, CY = B::NY - 1, CZ = B::NZ - 1;
+    const int bxi = cl.ix / CX, byi = cl.iy / CY, bzi = cl.iz / CZ;
+    const int lx = cl.ix - CX * bxi, ly = cl.iy - CY * byi, lz = cl.iz - CZ * bzi;
+    sy = B::NX;
+    sz = B::NX * B::NY;
+    i0 = ((bzi * g.by + byi) * g.bx + bxi) * (B::NX * B::NY * B::NZ) + (lz * sz + ly * sy + lx);
   }
   const float2 p00 = ld_pair<DT>(g.data, i0);
   const float2 p10 = ld_pair<DT>(g.data, i0 + sy);
@@ -795,20 +797,21 @@ __global__ void k_zero(unsigned* __restrict__ p, size_t n32) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n32; i += stride) p[i] = 0u;
 }
 
-template <typename T>
+template <typename T, int LAYOUT>
 __global__ void k_to_bricks(const T* __restrict__ src, T* __restrict__ dst, int nx, int ny, int nz, int bx, int by,
                             int bz) {
-  constexpr int NB = kBrickNodes * kBrickNodes * kBrickNodes;
+  using B = BrickShape<LAYOUT>;
+  constexpr int NB = B::NX * B::NY * B::NZ;
   const long long total = (long long)bx * by * bz * NB;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
     const long long brick = i / NB;
     const int local = (int)(i - brick * NB);
-    const int lx = local % kBrickNodes, ly = (local / kBrickNodes) % kBrickNodes, lz = local / (kBrickNodes * kBrickNodes);
+    const int lx = local % B::NX, ly = (local / B::NX) % B::NY, lz = local / (B::NX * B::NY);
     const int bxi = (int)(brick % bx), byi = (int)((brick / bx) % by), bzi = (int)(brick / ((long long)bx * by));
-    const int x = min(bxi * kBrickCells + lx, nx - 1);
-    const int y = min(byi * kBrickCells + ly, ny - 1);
-    const int z = min(bzi * kBrickCells + lz, nz - 1);
+    const int x = min(bxi * (B::NX - 1) + lx, nx - 1);
+    const int y = min(byi * (B::NY - 1) + ly, ny - 1);
+    const int z = min(bzi * (B::NZ - 1) + lz, nz - 1);
     dst[i] = src[((long long)z * ny + y) * nx + x];
   }
 }
@@ -853,6 +856,8 @@ hipError_t fwd_layout(const FwdArgs& a, int layout, int block, int vpt, int pers
                       bool from_cand, hipStream_t s) {
   if (layout == FC_LAYOUT_BRICK)
     return fwd_block<DT, FC_LAYOUT_BRICK>(a, block, vpt, persistent, xcd, grid, from_cand, s);
+  if (layout == FC_LAYOUT_SLAB)
+    return fwd_block<DT, FC_LAYOUT_SLAB>(a, block, vpt, persistent, xcd, grid, from_cand, s);
   return fwd_block<DT, FC_LAYOUT_LINEAR>(a, block, vpt, persistent, xcd, grid, from_cand, s);
 }
 
@@ -868,6 +873,22 @@ hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
   const long long n = (long long)a.n_env * 7 + (shared_v ? 3 * nv : 0);
   hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, shared_v, nv);
   return hipGetLastError();
+}
+
+template <int DT>
+hipError_t bwd_layout(const BwdArgs& a, int layout, hipStream_t s) {
+  if (layout == FC_LAYOUT_BRICK) return bwd_launch<DT, FC_LAYOUT_BRICK>(a, s);
+  if (layout == FC_LAYOUT_SLAB) return bwd_launch<DT, FC_LAYOUT_SLAB>(a, s);
+  return bwd_launch<DT, FC_LAYOUT_LINEAR>(a, s);
+}
+
+hipError_t bwd_dtype(const BwdArgs& a, int dtype, int layout, hipStream_t s) {
+  switch (dtype) {
+    case kF32: return bwd_layout<kF32>(a, layout, s);
+    case kF16: return bwd_layout<kF16>(a, layout, s);
+    case kBF16: return bwd_layout<kBF16>(a, layout, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -891,13 +912,7 @@ hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, in
 
 hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  const bool brick = layout == FC_LAYOUT_BRICK;
-  switch (dtype) {
-    case kF32: return brick ? bwd_launch<kF32, FC_LAYOUT_BRICK>(a, s) : bwd_launch<kF32, FC_LAYOUT_LINEAR>(a, s);
-    case kF16: return brick ? bwd_launch<kF16, FC_LAYOUT_BRICK>(a, s) : bwd_launch<kF16, FC_LAYOUT_LINEAR>(a, s);
-    case kBF16: return brick ? bwd_launch<kBF16, FC_LAYOUT_BRICK>(a, s) : bwd_launch<kBF16, FC_LAYOUT_LINEAR>(a, s);
-  }
-  return hipErrorInvalidValue;
+  return bwd_dtype(a, dtype, layout, s);
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
@@ -910,18 +925,30 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_to_bricks(const void* src, void* dst, int elem, int nx, int ny, int nz, int bx, int by, int bz,
-                            hipStream_t s) {
-  const long long total = (long long)bx * by * bz * kBrickNodes * kBrickNodes * kBrickNodes;
+hipError_t launch_to_bricks(const void* src, void* dst, int elem, int layout, int nx, int ny, int nz, int bx, int by,
+                            int bz, hipStream_t s) {
+  int bnx, bny, bnz;
+  brick_nodes(layout, bnx, bny, bnz);
+  const long long total = (long long)bx * by * bz * bnx * bny * bnz;
   long long blocks = (total + 255) / 256;
   if (blocks > 65535) blocks = 65535;
   if (blocks < 1) blocks = 1;
-  if (elem == 4)
-    hipLaunchKernelGGL(k_to_bricks<float>, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const float*>(src),
-                       static_cast<float*>(dst), nx, ny, nz, bx, by, bz);
-  else
-    hipLaunchKernelGGL(k_to_bricks<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       static_cast<const uint16_t*>(src), static_cast<uint16_t*>(dst), nx, ny, nz, bx, by, bz);
+  const dim3 gd((unsigned)blocks), bd(256);
+  if (elem == 4) {
+    const float* f = static_cast<const float*>(src);
+    float* d = static_cast<float*>(dst);
+    if (layout == FC_LAYOUT_SLAB)
+      hipLaunchKernelGGL((k_to_bricks<float, FC_LAYOUT_SLAB>), gd, bd, 0, s, f, d, nx, ny, nz, bx, by, bz);
+    else
+      hipLaunchKernelGGL((k_to_bricks<float, FC_LAYOUT_BRICK>), gd, bd, 0, s, f, d, nx, ny, nz, bx, by, bz);
+  } else {
+    const uint16_t* f = static_cast<const uint16_t*>(src);
+    uint16_t* d = static_cast<uint16_t*>(dst);
+    if (layout == FC_LAYOUT_SLAB)
+      hipLaunchKernelGGL((k_to_bricks<uint16_t, FC_LAYOUT_SLAB>), gd, bd, 0, s, f, d, nx, ny, nz, bx, by, bz);
+    else
+      hipLaunchKernelGGL((k_to_bricks<uint16_t, FC_LAYOUT_BRICK>), gd, bd, 0, s, f, d, nx, ny, nz, bx, by, bz);
+  }
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfactory_
 
 FC_OK, FC_ERR_NULL, FC_ERR_SHAPE, FC_ERR_DTYPE, FC_ERR_RANGE, FC_ERR_WORKSPACE, FC_ERR_HIP, FC_ERR_UNSUPPORTED = range(8)
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
-LAYOUTS = {"linear": 0, "brick": 1}
+LAYOUTS = {"linear": 0, "brick": 1, "slab": 2}
 MAX_TYPES = 8
 MAX_BINS = 64
 
@@ -79,8 +79,9 @@ SIGNATURES = {
                                   C.POINTER(fc_grads), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
     "fc_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fc_graph_destroy": (None, [C.c_void_p]),
-    "fc_grid_brick_bytes": (C.c_size_t, [C.POINTER(fc_grid)]),
-    "fc_grid_to_bricks": (C.c_int, [C.POINTER(fc_grid), C.c_void_p, C.c_size_t, C.POINTER(fc_grid), C.c_void_p]),
+    "fc_grid_brick_bytes": (C.c_size_t, [C.POINTER(fc_grid), C.c_int32]),
+    "fc_grid_to_bricks": (C.c_int, [C.POINTER(fc_grid), C.c_int32, C.c_void_p, C.c_size_t, C.POINTER(fc_grid),
+                                    C.c_void_p]),
     "fc_autotune_load": (C.c_int32, [C.c_char_p]),
     "fc_batch_signature": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32]),
     "fc_status_str": (C.c_char_p, [C.c_int]),
@@ -160,13 +161,14 @@ class Batch:
             nz, ny, nx = vals.shape
             d = fc_grid(C.c_void_p(t.data_ptr()), DTYPES[g.dtype], 0, nx, ny, nz,
                         (C.c_float * 3)(*[float(np.float32(o)) for o in g.origin]), float(np.float32(g.h)))
-            if layout == "brick":
-                nb = L.fc_grid_brick_bytes(C.byref(d))
+            if layout != "linear":
+                lay = LAYOUTS[layout]
+                nb = L.fc_grid_brick_bytes(C.byref(d), lay)
                 if nb == 0:
-                    raise ValueError("grid cannot be bricked")
+                    raise ValueError(f"grid cannot be stored as {layout}")
                 bt = torch.empty(nb, dtype=torch.uint8, device=self.device)
                 out = fc_grid()
-                _check(L.fc_grid_to_bricks(C.byref(d), C.c_void_p(bt.data_ptr()), nb, C.byref(out),
+                _check(L.fc_grid_to_bricks(C.byref(d), lay, C.c_void_p(bt.data_ptr()), nb, C.byref(out),
                                            _stream(None)), "fc_grid_to_bricks")
                 torch.cuda.synchronize(self.device)
                 self._keep.append(t)

@@ -110,11 +110,13 @@ def test_null_arguments(L):
 def test_brick_size_query(L):
     g = fc.fc_grid(C.c_void_p(FAKE), 0, 0, 256, 256, 512, (C.c_float * 3)(0, 0, 0), 1e-4)
     bx, by, bz = -(-255 // 3), -(-255 // 3), -(-511 // 3)
-    assert L.fc_grid_brick_bytes(C.byref(g)) == bx * by * bz * 64 * 4
+    assert L.fc_grid_brick_bytes(C.byref(g), 1) == bx * by * bz * 64 * 4
+    assert L.fc_grid_brick_bytes(C.byref(g), 2) == bx * by * 511 * 32 * 4  # slabs: 4x4x2 nodes, 3x3x1 cells
+    assert L.fc_grid_brick_bytes(C.byref(g), 0) == 0
     g.dtype = 1
-    assert L.fc_grid_brick_bytes(C.byref(g)) == bx * by * bz * 64 * 2
+    assert L.fc_grid_brick_bytes(C.byref(g), 1) == bx * by * bz * 64 * 2
     g.nx = 1
-    assert L.fc_grid_brick_bytes(C.byref(g)) == 0
+    assert L.fc_grid_brick_bytes(C.byref(g), 1) == 0
 
 
 def test_autotune_cache_parse(L, tmp_path):

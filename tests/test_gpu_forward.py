@@ -130,13 +130,19 @@ def test_env_order_does_not_change_contacts(nutbolt24):
         assert_same(o, ref_o)
 
 
-def test_brick_layout_bit_identical(nutbolt24):
+@pytest.mark.parametrize("layout", ["brick", "slab"])
+def test_brick_layouts_bit_identical(nutbolt24, layout):
     w, b, pose = nutbolt24
     ref_c, ref_o = run(b, pose)
-    bb = fc.Batch.from_workload(w, layout="brick")
+    bb = fc.Batch.from_workload(w, layout=layout)
     c, o = run(bb, pose)
     assert_same(c, ref_c)
     assert_same(o, ref_o)
+    g_ref, g_b = b.new_grads(per_env=True), bb.new_grads(per_env=True)
+    fc.fc_sdf_query_backward(b, pose, 1e4, g_ref)
+    fc.fc_sdf_query_backward(bb, pose, 1e4, g_b)
+    assert_same(to_np({k: v for k, v in g_b.items() if k != "per_env"}),
+                to_np({k: v for k, v in g_ref.items() if k != "per_env"}))
 
 
 def _sphere_grid(n=24, h=1.0 / 16):
