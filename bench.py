@@ -38,7 +38,7 @@ def log(*a):
 
 
 # the configuration the bench times (and the full-size parity tests check)
-BENCH_LAYOUT = "linear"
+BENCH_LAYOUT = "brick"
 BENCH_LAUNCH = dict(block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=1)
 TUNE_CACHE = os.path.join(ROOT, "paper_2205_03532_amd", "autotune.json")
 
@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-env", type=int, default=1000)
-    ap.add_argument("--layout", default=None, choices=[None, "linear", "brick"])
+    ap.add_argument("--layout", default=None, choices=[None, "linear", "brick", "slab"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--cpu-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -116,12 +116,12 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="nutbolt", choices=["nutbolt", "mixed", "torus"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--layout", default="linear", choices=["linear", "brick"])
+    ap.add_argument("--layout", default="brick", choices=["linear", "brick", "slab"])
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     w = _workload(a.workload, a.dtype)
-    batch = fc.Batch.from_workload(w, layout=a.layout)
+    batch = fc.Batch.from_workload(w, layout=a.layout, env_order=fc.locality_order(w))
     pose = fc.pose_tensor(w.pose)
     print(f"tuning {w.name} ({a.dtype}, {a.layout}): {batch.Q} queries", flush=True)
     best, _ = tune(batch, pose, reps=a.reps, log=lambda s: print(s, flush=True))

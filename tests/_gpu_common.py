@@ -28,18 +28,19 @@ def position_error_voxels(o):
     return (6.0 * ULP32 * scale) / o["h"][:, None] + 2.0 * ULP32 * np.abs(o["u"]) + 1e-7
 
 
-def gradient_sensitivity(w, o):
+def gradient_sensitivity(w, o, cells=None):
     """Per query: S = max |mixed second difference| of the cell's corners
     (value units), which bounds |d grad / d t| of the trilinear interpolant
     inside the cell; and cmax = max |corner value| (the scale of the FP32
-    rounding in the nested lerps)."""
-    S = np.zeros(len(o["phi"]))
-    cmax = np.zeros(len(o["phi"]))
+    rounding in the nested lerps).  ``cells`` overrides o["cell"]."""
+    cells = o["cell"] if cells is None else cells
+    S = np.zeros(len(cells))
+    cmax = np.zeros(len(cells))
     for e in np.unique(o["env"]):
         sel = np.nonzero(o["env"] == e)[0]
         g = w.grids[int(w.env_grid[e])]
         vals = OQ.grid_values_f64(g.values, g.dtype)
-        c = o["cell"][sel]
+        c = cells[sel]
         ix, iy, iz = c[:, 0], c[:, 1], c[:, 2]
         C = {(a, b, d): vals[iz + d, iy + b, ix + a] for a in (0, 1) for b in (0, 1) for d in (0, 1)}
         m = np.zeros(len(sel))
@@ -77,7 +78,7 @@ def fma32(a, b, c):
     midpoint; those elements are redone in exact rational arithmetic."""
     from fractions import Fraction
 
-    a64, b64, c64 = (np.asarray(x, np.float32).astype(np.float64) for x in (a, b, c))
+    a64, b64, c64 = np.broadcast_arrays(*(np.asarray(x, np.float32).astype(np.float64) for x in (a, b, c)))
     s = a64 * b64 + c64
     r = s.astype(np.float32)
     r64 = r.astype(np.float64)
@@ -158,25 +159,41 @@ def oracle_rows(w, envs):
     return o
 
 
-def _alt_normals(w, o, idx):
-    """Oracle normals at points nudged across nearby cell faces, on every
-    combination of axes (near an edge or corner either neighbouring cell is
-    valid)."""
+def normal_bound(w, o, du, cells=None, grads=None):
+    """|n_fp32 - n_fp64| bound per query: 2 (sqrt(3) S du + 8 ulp cmax) / |g| (+ NORMAL_TOL)."""
+    grads = o["grad"] if grads is None else grads
+    S, cmax = gradient_sensitivity(w, o, cells)
+    gvox = np.linalg.norm(grads, axis=1) * o["h"]
+    return NORMAL_TOL + 2.0 * (math.sqrt(3.0) * S * du + 8.0 * ULP32 * cmax) / np.maximum(gvox, 1e-30)
+
+
+def _alt_normals(w, o, idx, band):
+    """Oracle normals, with their own error bounds, at points nudged across
+    nearby cell faces on every combination of the near axes (within the FP32
+    position error either neighbouring cell is valid)."""
     import itertools
 
     alts = []
+    sub = {k: (v[idx] if hasattr(v, "__len__") and len(v) == len(o["phi"]) else v) for k, v in o.items()}
+    t = sub["u"] - np.floor(sub["u"])
+    near = (t < band[idx]) | (t > 1 - band[idx])
+    du = np.max(position_error_voxels(sub), axis=1)
     for sgn in itertools.product((-1.0, 0.0, 1.0), repeat=3):
         if sgn == (0.0, 0.0, 0.0):
             continue
-        x = o["x_b"][idx] + np.asarray(sgn)[None, :] * (3 * FACE_BAND * o["h"][idx])[:, None]
+        step = np.asarray(sgn)[None, :] * near * (2.0 * band[idx] * sub["h"][:, None])
+        x = sub["x_b"] + step
         n = np.zeros_like(x)
-        for e in np.unique(o["env"][idx]):
-            sel = o["env"][idx] == e
+        grads = np.zeros_like(x)
+        cells = np.zeros_like(sub["cell"])
+        for e in np.unique(sub["env"]):
+            sel = sub["env"] == e
             g = w.grids[int(w.env_grid[e])]
             vals = OQ.grid_values_f64(g.values, g.dtype)
-            _, grad, _, _ = OQ.sample(vals, g.origin, g.h, g.dims, x[sel])
-            n[sel], _, _ = OQ.normals_and_bins(grad, w.bins)
-        alts.append(n)
+            _, grads[sel], _, cells[sel] = OQ.sample(vals, g.origin, g.h, g.dims, x[sel])
+            n[sel], _, _ = OQ.normals_and_bins(grads[sel], w.bins)
+        tol = normal_bound(w, sub, du, cells, grads)
+        alts.append((n, tol))
     return alts
 
 
@@ -212,28 +229,27 @@ def check_candidates(w, cand, envs, depth_tol=DEPTH_TOL_F32, o=None):
     bad = (g_cand != o["cand"]) & ~amb & both
     assert not bad.any(), f"candidate mismatch at rows {rows[bad][:10]}"
     assert not (g_cand & ~g_inside).any()
-    # normals: within the FP32 bound; near a cell face either cell's normal is valid.
-    # |dn| <= 2 |dg| / |g| with |dg| <= sqrt(3) S du + 8 ulp cmax (S: mixed second
-    # differences, du: FP32 position error in voxels, cmax: largest corner, whose
-    # ulp sets the rounding of the nested lerps; |g| in value units per voxel).
-    du = np.max(position_error_voxels(o), axis=1)
-    gvox = np.linalg.norm(o["grad"], axis=1) * o["h"]
-    S, cmax = gradient_sensitivity(w, o)
-    tol = NORMAL_TOL + 2.0 * (math.sqrt(3.0) * S * du + 8.0 * ULP32 * cmax) / np.maximum(gvox, 1e-30)
+    # normals: within the FP32 bound; within the FP32 position error of a cell
+    # face either cell's normal is valid.
+    du3 = position_error_voxels(o)
+    du = np.max(du3, axis=1)
+    tol = normal_bound(w, o, du)
+    band = np.maximum(FACE_BAND, 2.0 * du)
     t = o["u"] - np.floor(o["u"])
-    near_face = np.any((t < FACE_BAND) | (t > 1 - FACE_BAND), axis=1) & both
+    near_face = np.any((t < band[:, None]) | (t > 1 - band[:, None]), axis=1) & both
     nerr = np.linalg.norm(nrm - o["normal"], axis=1)
     bad = (nerr > tol) & both & ~near_face
     assert not bad.any(), f"normal mismatch at rows {rows[bad][:10]} err {nerr[bad][:5]} tol {tol[bad][:5]}"
-    stats["max_normal_err"] = float(nerr[both & ~near_face].max()) if (both & ~near_face).any() else 0.0
-    stats["max_normal_err_over_bound"] = float((nerr / tol)[both & ~near_face].max()) if (both & ~near_face).any() else 0.0
+    far = both & ~near_face
+    stats["max_normal_err"] = float(nerr[far].max()) if far.any() else 0.0
+    stats["max_normal_err_over_bound"] = float((nerr / tol)[far].max()) if far.any() else 0.0
     nf = np.nonzero(near_face & (nerr > tol))[0]
     stats["face_band"] = int(near_face.sum())
-    alts = _alt_normals(w, o, nf) if len(nf) else []
+    alts = _alt_normals(w, o, nf, band) if len(nf) else []
     if len(nf):
         ok = np.zeros(len(nf), bool)
-        for a in alts:
-            ok |= np.linalg.norm(nrm[nf] - a, axis=1) <= tol[nf] + 1e-6
+        for a, ta in alts:
+            ok |= np.linalg.norm(nrm[nf] - a, axis=1) <= ta
         assert ok.all(), f"near-face normal mismatch at rows {rows[nf[~ok]][:10]}"
     # bins, where both sides call it a candidate: the GPU's bin must be an
     # argmax of the FP64 dots up to the normal error bound
@@ -244,8 +260,10 @@ def check_candidates(w, cand, envs, depth_tol=DEPTH_TOL_F32, o=None):
     okb = (b == o["bin"]) | (dgpu >= dmax - 2.0 * tol - 1e-7)
     if len(nf):
         dirs = np.asarray(w.bins, np.float32).astype(np.float64)
-        for a in alts:
-            okb[nf] |= np.argmax(a @ dirs, axis=1) == b[nf]
+        for a, ta in alts:
+            da = a @ dirs
+            dg = np.take_along_axis(da, np.clip(b[nf], 0, da.shape[1] - 1)[:, None], axis=1)[:, 0]
+            okb[nf] |= dg >= da.max(axis=1) - 2.0 * ta - 1e-7
     bad = cc & ~okb
     assert not bad.any(), f"bin mismatch at rows {rows[bad][:10]}"
     stats["bin_near_tie"] = int((cc & (b != o["bin"])).sum())
