@@ -176,12 +176,13 @@ def _alt_normals(w, o, idx, band):
     alts = []
     sub = {k: (v[idx] if hasattr(v, "__len__") and len(v) == len(o["phi"]) else v) for k, v in o.items()}
     t = sub["u"] - np.floor(sub["u"])
-    near = (t < band[idx]) | (t > 1 - band[idx])
+    bnd = band[idx][:, None]
+    near = (t < bnd) | (t > 1 - bnd)
     du = np.max(position_error_voxels(sub), axis=1)
     for sgn in itertools.product((-1.0, 0.0, 1.0), repeat=3):
         if sgn == (0.0, 0.0, 0.0):
             continue
-        step = np.asarray(sgn)[None, :] * near * (2.0 * band[idx] * sub["h"][:, None])
+        step = np.asarray(sgn)[None, :] * near * (2.0 * bnd * sub["h"][:, None])
         x = sub["x_b"] + step
         n = np.zeros_like(x)
         grads = np.zeros_like(x)
