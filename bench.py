@@ -43,6 +43,61 @@ BENCH_LAUNCH = dict(block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=1
 TUNE_CACHE = os.path.join(ROOT, "paper_2205_03532_amd", "autotune.json")
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "paper_2205_03532_amd", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2205_03532_amd", "csrc", f) for f in ("fc_kernels.hip", "fc_internal.h")]
+COPY_PROBE_BYTES = 256 << 20
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _median_counter(csv_dir, kernel_substr, counter):
+    import csv
+    import glob
+
+    vals = []
+    for path in glob.glob(os.path.join(csv_dir, "*counter_collection.csv")):
+        for r in csv.DictReader(open(path)):
+            if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} samples for {kernel_substr} under {csv_dir}")
+    return sorted(vals)[len(vals) // 2]
+
+
+def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this bench (and of
+    --copy-probe, for calibration) into bytes per launch of each kernel."""
+    f_scale = COPY_PROBE_BYTES / 1024 / _median_counter(copy_fetch_dir, "copyBuffer", "FETCH_SIZE")
+    w_scale = COPY_PROBE_BYTES / 1024 / _median_counter(copy_write_dir, "copyBuffer", "WRITE_SIZE")
+    rec = {"kernel_source_sha256": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale}
+    for k in ("k_forward", "k_backward"):
+        fetch = _median_counter(fetch_dir, k, "FETCH_SIZE") * 1024 * f_scale
+        write = _median_counter(write_dir, k, "WRITE_SIZE") * 1024 * w_scale
+        rec[k] = {"fetch_bytes": fetch, "write_bytes": write}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def measured_traffic(kernel):
+    """HBM-side bytes per launch of `kernel` from the recorded counters, or None
+    when the kernels changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    if rec.get("kernel_source_sha256") != kernel_source_hash() or kernel not in rec:
+        return None
+    return rec[kernel]["fetch_bytes"] + rec[kernel]["write_bytes"]
+
+
 def make_batch(w, device, layout=None, launch=None):
     """The bench's batch: envs scheduled in spatial order, the tuned launch shape
     (autotune cache entry for this signature if present, else BENCH_LAUNCH)."""
@@ -108,7 +163,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates rocprof byte counters) and exit")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the measured bytes per launch from rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
+
+    if args.record_traffic:
+        record_traffic(*args.record_traffic)
+        return
 
     if args.copy_probe:
         import torch
@@ -175,10 +236,11 @@ def main():
     bpq = alg_bytes_per_query(args.dtype)
     f_avg, b_avg = float(fwd_ms.mean()), float(bwd_ms.mean())
     if f_avg >= b_avg:
-        kname, kms = "k_forward (fused query + reduction)", f_avg
+        kname, kkey, kms = "k_forward (fused query + reduction)", "k_forward", f_avg
     else:
-        kname, kms = "k_backward (penalty adjoint)", b_avg
+        kname, kkey, kms = "k_backward (penalty adjoint)", "k_backward", b_avg
     achieved = bpq * Q / (kms * 1e-3) / 1e9
+    traffic = measured_traffic(kkey) if (args.layout or BENCH_LAYOUT) == BENCH_LAYOUT and args.dtype == "f32" else None
 
     # accuracy of the timed configuration on a sample (outside the timed region)
     cand = batch.new_candidates()
@@ -222,7 +284,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "alg_bytes_per_query": bpq,
         },
     }

@@ -742,33 +742,45 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
 
 }
 
-// Fixed-order combine of the adjoint's partial sums: one thread per
-// (env, value) for the loss and twist, then one per (component, mesh vertex)
-// for the shared vertex gradients.  Summation order: tiles in order, chunks
-// in order.  Partial offsets are computed, not loaded, so every thread's
-// loads are independent and in flight together.
-__global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, long long n_vert_total) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long n_pose = (long long)A.n_env * 7;
-  if (i < n_pose) {
-    const int e = (int)(i / 7);
-    const int val = (int)(i - (long long)e * 7);
-    constexpr int NW = kBwdBlock / 64;
+// Fixed-order combine of the adjoint's partial sums.  Workgroups
+// [0, pose_blocks) take one environment per wavefront: lane l sums the env's
+// partial rows l, l + 64, ... in order, then the lanes are combined by the
+// fixed DPP tree.  The remaining workgroups take one (component, vertex) per
+// thread and sum the chunks in order, loads issued eight at a time.
+constexpr int kCombineBatch = 8;
+
+__global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, long long n_vert_total,
+                                                     int pose_blocks) {
+  constexpr int NW = kBwdBlock / 64;
+  if ((int)blockIdx.x < pose_blocks) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= A.n_env) return;  // whole wavefront leaves together
+    const int lane = threadIdx.x & 63;
     const int n_rows = A.mesh_tiles[A.envs[e].gm >> 8] * NW;  // (tile, wave) rows in order
-    const float2* part = A.pose_part + (long long)A.env_tile_base[e] * NW * 8 + val;
-    float2 r = part[0];
-    for (int t = 1; t < n_rows; ++t) r = ncombine(r, part[(long long)t * 8]);
-    const float v = r.x + r.y;
-    if (val == 0) {
-      if (A.loss) A.loss[e] = v;
-    } else if (A.d_pose) {
-      const float up = A.upstream ? A.upstream[e] : 1.f;
-      A.d_pose[(long long)(val - 1) * A.n_env + e] = up * v;
+    const float2* base = A.pose_part + (long long)A.env_tile_base[e] * NW * 8;
+    float2 acc[7];
+#pragma unroll
+    for (int v = 0; v < 7; ++v) acc[v] = make_float2(0.f, 0.f);
+    for (int r = lane; r < n_rows; r += 64) {
+      const float2* row = base + (long long)r * 8;
+#pragma unroll
+      for (int v = 0; v < 7; ++v) acc[v] = ncombine(acc[v], row[v]);
+    }
+    float2 tot[7];
+#pragma unroll
+    for (int v = 0; v < 7; ++v) tot[v] = wave_sum_pair(acc[v]);
+    if (lane == 0) {
+      if (A.loss) A.loss[e] = tot[0].x + tot[0].y;
+      if (A.d_pose) {
+        const float up = A.upstream ? A.upstream[e] : 1.f;
+#pragma unroll
+        for (int v = 1; v < 7; ++v) A.d_pose[(long long)(v - 1) * A.n_env + e] = up * (tot[v].x + tot[v].y);
+      }
     }
     return;
   }
   if (!shared_v) return;
-  const long long jj = i - n_pose;
+  const long long jj = (long long)(blockIdx.x - pose_blocks) * blockDim.x + threadIdx.x;
   if (jj >= 3 * n_vert_total) return;
   const int comp = (int)(jj / n_vert_total);
   long long j = jj - (long long)comp * n_vert_total;
@@ -783,8 +795,14 @@ __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, lo
   const float2* p = A.vert_part + A.mesh_vpart0[m] + comp * n + j;
   const long long stride = 3 * n;
   float2 r = make_float2(0.f, 0.f);
-  if (nc > 0) r = p[0];
-  for (int c = 1; c < nc; ++c) r = ncombine(r, p[c * stride]);
+  for (int c0 = 0; c0 < nc; c0 += kCombineBatch) {
+    float2 buf[kCombineBatch];
+#pragma unroll
+    for (int b = 0; b < kCombineBatch; ++b) buf[b] = (c0 + b < nc) ? p[(c0 + b) * stride] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < kCombineBatch; ++b)
+      if (c0 + b < nc) r = (c0 + b == 0) ? buf[b] : ncombine(r, buf[b]);
+  }
   A.d_verts[A.mesh_voff[m] + comp * n + j] = r.x + r.y;
 }
 
@@ -870,8 +888,10 @@ hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
   const int shared_v = (a.d_verts != nullptr) && !a.per_env;
   long long nv = 0;
   for (int m = 0; m < a.n_meshes; ++m) nv += a.meshes[m].n;
-  const long long n = (long long)a.n_env * 7 + (shared_v ? 3 * nv : 0);
-  hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, shared_v, nv);
+  const int pose_blocks = (a.n_env + 3) / 4;
+  const long long vert_blocks = shared_v ? (3 * nv + 255) / 256 : 0;
+  hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)(pose_blocks + vert_blocks)), dim3(256), 0, s, a, shared_v, nv,
+                     pose_blocks);
   return hipGetLastError();
 }
 
