@@ -1,12 +1,14 @@
 """Throughput of the vertex-vs-SDF contact path on one MI355X.
 
-One step = the whole hot path over one batch: the fused query + contact
-reduction kernel (transform, trilinear SDF value and gradient, candidate,
-normal bin, deepest-per-bin reduction, winner records), then the adjoint
-kernel of the penetration penalty (loss, per-env twist gradient, shared
-vertex gradient).  Workload: 1000 hex nuts (16,396 vertices each) on one
-M16-like threaded bolt SDF of 256x256x512 FP32 samples (h = 0.1 mm), K = 32
-normal bins, k = 1e4; inputs resident in HBM before timing.
+One step = the whole hot path over one batch, as one
+``fc_sdf_query_and_backward`` call: per query the transform, trilinear SDF
+value and gradient, candidate, normal bin and deepest-per-bin reduction with
+the winner records (the forward), and the adjoint of the penetration penalty
+(loss, per-env twist gradient, shared vertex gradient), from one gather.
+Workload: 1000 hex nuts (16,396 vertices each) on one M16-like threaded bolt
+SDF of 256x256x512 FP32 samples (h = 0.1 mm), K = 32 normal bins, k = 1e4;
+inputs resident in HBM before timing.  The separate forms (``fc_sdf_query``
+alone; then ``fc_sdf_query_backward``) are timed after the step, outside it.
 
 Prints ONE JSON line (rank 0).  ``value`` is queries per second of the whole
 step (one query = one (env, vertex) pair, counted once per step).  The
@@ -58,17 +60,26 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def _median_counter(csv_dir, kernel_substr, counter):
+PROFILED_KERNELS = ("k_query_backward", "k_forward", "k_backward")
+
+
+def _median_counter(csv_dir, kernel, counter, required=True):
+    """Median per-dispatch value of `counter` for kernel `kernel` (matched as
+    '::kernel<' in the demangled name, so k_backward does not match
+    k_query_backward)."""
     import csv
     import glob
 
+    pat = f"::{kernel}<"
     vals = []
     for path in glob.glob(os.path.join(csv_dir, "*counter_collection.csv")):
         for r in csv.DictReader(open(path)):
-            if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            if pat in r["Kernel_Name"] and r["Counter_Name"] == counter:
                 vals.append(float(r["Counter_Value"]))
     if not vals:
-        raise SystemExit(f"no {counter} samples for {kernel_substr} under {csv_dir}")
+        if required:
+            raise SystemExit(f"no {counter} samples for {kernel} under {csv_dir}")
+        return None
     return sorted(vals)[len(vals) // 2]
 
 
@@ -78,10 +89,12 @@ def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     f_scale = COPY_PROBE_BYTES / 1024 / _median_counter(copy_fetch_dir, "copyBuffer", "FETCH_SIZE")
     w_scale = COPY_PROBE_BYTES / 1024 / _median_counter(copy_write_dir, "copyBuffer", "WRITE_SIZE")
     rec = {"kernel_source_sha256": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale}
-    for k in ("k_forward", "k_backward"):
-        fetch = _median_counter(fetch_dir, k, "FETCH_SIZE") * 1024 * f_scale
-        write = _median_counter(write_dir, k, "WRITE_SIZE") * 1024 * w_scale
-        rec[k] = {"fetch_bytes": fetch, "write_bytes": write}
+    for k in PROFILED_KERNELS:
+        fetch = _median_counter(fetch_dir, k, "FETCH_SIZE", required=False)
+        write = _median_counter(write_dir, k, "WRITE_SIZE", required=False)
+        if fetch is None or write is None:
+            continue
+        rec[k] = {"fetch_bytes": fetch * 1024 * f_scale, "write_bytes": write * 1024 * w_scale}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
@@ -208,37 +221,50 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        fc.fc_sdf_query(batch, pose, fused_out=out)
-        fc.fc_sdf_query_backward(batch, pose, K_PENALTY, grads)
+        fc.fc_sdf_query_and_backward(batch, pose, out, K_PENALTY, grads)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
+    # timed region: K steps, each bracketed by HIP events on the stream the kernels run on
     n = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(n):
         ev[i][0].record(stream)
-        fc.fc_sdf_query(batch, pose, fused_out=out)
+        step()
         ev[i][1].record(stream)
-        fc.fc_sdf_query_backward(batch, pose, K_PENALTY, grads)
-        ev[i][2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-
-    fwd_ms = np.array([ev[i][0].elapsed_time(ev[i][1]) for i in range(n)])
-    bwd_ms = np.array([ev[i][1].elapsed_time(ev[i][2]) for i in range(n)])
+    one_ms = np.array([ev[i][0].elapsed_time(ev[i][1]) for i in range(n)])
     ms_step = wall * 1e3 / n
     value = Q * n / wall
 
+    # the separate forms, for comparison (not part of the step)
+    out2 = batch.new_contacts()
+    grads2 = batch.new_grads(per_env=False)
+    for _ in range(args.warmup):
+        fc.fc_sdf_query(batch, pose, fused_out=out2)
+        fc.fc_sdf_query_backward(batch, pose, K_PENALTY, grads2)
+    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
+    torch.cuda.synchronize()
+    for i in range(n):
+        ev2[i][0].record(stream)
+        fc.fc_sdf_query(batch, pose, fused_out=out2)
+        ev2[i][1].record(stream)
+        fc.fc_sdf_query_backward(batch, pose, K_PENALTY, grads2)
+        ev2[i][2].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = np.array([ev2[i][0].elapsed_time(ev2[i][1]) for i in range(n)])
+    bwd_ms = np.array([ev2[i][1].elapsed_time(ev2[i][2]) for i in range(n)])
+    same = all(torch.equal(out[k], out2[k]) for k in out) and all(
+        torch.equal(grads[k], grads2[k]) for k in ("loss", "d_pose", "d_verts"))
+
     bpq = alg_bytes_per_query(args.dtype)
-    f_avg, b_avg = float(fwd_ms.mean()), float(bwd_ms.mean())
-    if f_avg >= b_avg:
-        kname, kkey, kms = "k_forward (fused query + reduction)", "k_forward", f_avg
-    else:
-        kname, kkey, kms = "k_backward (penalty adjoint)", "k_backward", b_avg
+    o_avg, f_avg, b_avg = float(one_ms.mean()), float(fwd_ms.mean()), float(bwd_ms.mean())
+    kname, kkey, kms = "k_query_backward (one-pass query, reduction and penalty adjoint)", "k_query_backward", o_avg
     achieved = bpq * Q / (kms * 1e-3) / 1e9
     traffic = measured_traffic(kkey) if (args.layout or BENCH_LAYOUT) == BENCH_LAYOUT and args.dtype == "f32" else None
 
@@ -265,8 +291,8 @@ def main():
         "config": {
             "workload": f"nut-on-bolt: {w.n_env} envs x {w.meshes[0].n}-vertex hex nut (M16-like internal "
                         f"thread) vs one {'x'.join(map(str, w.grids[0].dims))} {args.dtype} bolt SDF "
-                        f"(h = 0.1 mm), K = {w.K} bins; step = fused query+reduce, then penalty adjoint "
-                        f"(k = 1e4, shared vertex gradients)",
+                        f"(h = 0.1 mm), K = {w.K} bins; step = one-pass query + contact reduction + penalty "
+                        f"adjoint (k = 1e4, shared vertex gradients)",
             "n_env": w.n_env,
             "queries_per_step": Q,
             "layout": args.layout or BENCH_LAYOUT,
@@ -275,7 +301,9 @@ def main():
         },
         "fwd_queries_per_s": Q / (f_avg * 1e-3),
         "fwd_bwd_queries_per_s": value,
-        "kernel_ms": {"forward": f_avg, "backward": b_avg},
+        "separate_fwd_then_bwd_queries_per_s": Q / ((f_avg + b_avg) * 1e-3),
+        "separate_equals_one_pass": bool(same),
+        "kernel_ms": {"query_and_backward": o_avg, "forward": f_avg, "backward": b_avg},
         "max_depth_err_m": derr,
         "roofline": {
             "bound": "hbm",

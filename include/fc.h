@@ -240,12 +240,25 @@ fc_status fc_contact_reduce(const fc_batch* batch, const float* pose, const fc_c
 fc_status fc_sdf_query_backward(const fc_batch* batch, const float* pose, float k, const float* upstream,
                                 const fc_grads* out, void* ws, size_t ws_bytes, void* stream);
 
+/* fc_sdf_query with fused_out, then fc_sdf_query_backward, computed in one
+ * pass over the queries: each query is located, gathered and interpolated
+ * once and feeds both the contact reduction and the penalty adjoint.  Every
+ * output is bit-identical to the two separate calls (the contacts come from
+ * an order-independent integer max; the adjoint keeps its fixed summation
+ * order).  For callers that need contacts and penalty gradients in the same
+ * step with the upstream weights already known.  Arguments as for the two
+ * calls; fused_out and grads are both required (else FC_ERR_NULL). */
+fc_status fc_sdf_query_and_backward(const fc_batch* batch, const float* pose, const fc_contacts* fused_out, float k,
+                                    const float* upstream, const fc_grads* grads, void* ws, size_t ws_bytes,
+                                    void* stream);
+
 /* ---- graphs ------------------------------------------------------------- */
 
 typedef struct fc_graph fc_graph; /* opaque instantiated hipGraph */
 
 /* Capture one step -- the fused forward (if fused_out) and the backward (if
- * grads) -- into an instantiated hipGraph on a private capture stream.  The
+ * grads), as one fc_sdf_query_and_backward pass when both are given -- into
+ * an instantiated hipGraph on a private capture stream.  The
  * graph replays with the pointers given here.  Validation as for the calls. */
 fc_status fc_graph_create(const fc_batch* batch, const float* pose, const fc_contacts* fused_out, float k,
                           const float* upstream, const fc_grads* grads, void* ws, size_t ws_bytes,

@@ -591,8 +591,7 @@ fc_status enqueue_forward(const fc_batch* b, const float* pose, const fc_candida
   return FC_OK;
 }
 
-fc_status enqueue_backward(const fc_batch* b, const float* pose, float k, const float* upstream, const fc_grads* out,
-                           void* ws, hipStream_t s) {
+BwdArgs make_bwd(const fc_batch* b, const float* pose, float k, const float* upstream, const fc_grads* out, void* ws) {
   BwdArgs a;
   std::memset(&a, 0, sizeof(a));
   fill_common(b, a.grids, a.meshes);
@@ -623,7 +622,29 @@ fc_status enqueue_backward(const fc_batch* b, const float* pose, float k, const 
   char* w = static_cast<char*>(ws);
   a.pose_part = reinterpret_cast<float2*>(w + b->off_pose);
   a.vert_part = reinterpret_cast<float2*>(w + b->off_vert);
+  return a;
+}
+
+fc_status enqueue_backward(const fc_batch* b, const float* pose, float k, const float* upstream, const fc_grads* out,
+                           void* ws, hipStream_t s) {
+  const BwdArgs a = make_bwd(b, pose, k, upstream, out, ws);
   FC_HIP(launch_backward(a, b->dtype, b->layout, s));
+  return FC_OK;
+}
+
+// fused query + reduce and the adjoint, from one gather per query
+fc_status enqueue_query_backward(const fc_batch* b, const float* pose, const fc_contacts* contacts, float k,
+                                 const float* upstream, const fc_grads* out, void* ws, hipStream_t s) {
+  const BwdArgs a = make_bwd(b, pose, k, upstream, out, ws);
+  const FwdArgs f = make_fwd(b, pose, nullptr, contacts, ws);
+  QueryExtra q;
+  std::memset(&q, 0, sizeof(q));
+  for (int i = 0; i < 3 * b->K; ++i) q.dirs[i] = b->dirs[i];
+  q.bin_lut = b->d_lut;
+  q.K = b->K;
+  q.margin = b->margin;
+  q.keys = f.keys;
+  FC_HIP(launch_query_backward(a, q, f, b->dtype, b->layout, s));
   return FC_OK;
 }
 
@@ -783,6 +804,16 @@ fc_status fc_sdf_query_backward(const fc_batch* b, const float* pose, float k, c
   return enqueue_backward(b, pose, k, upstream, out, ws, (hipStream_t)stream);
 }
 
+fc_status fc_sdf_query_and_backward(const fc_batch* b, const float* pose, const fc_contacts* fused_out, float k,
+                                    const float* upstream, const fc_grads* grads, void* ws, size_t ws_bytes,
+                                    void* stream) {
+  if (!b || !pose || !fused_out || !grads) return FC_ERR_NULL;
+  if (!contacts_ok(fused_out)) return FC_ERR_NULL;
+  fc_status s = validate_backward(b, pose, k, grads, ws, ws_bytes);
+  if (s != FC_OK) return s;
+  return enqueue_query_backward(b, pose, fused_out, k, upstream, grads, ws, (hipStream_t)stream);
+}
+
 struct fc_graph {
   hipGraphExec_t exec = nullptr;
 };
@@ -807,8 +838,12 @@ fc_status fc_graph_create(const fc_batch* b, const float* pose, const fc_contact
     (void)hipStreamDestroy(cs);
     return hip_fail(he);
   }
-  if (fused_out) s = enqueue_forward(b, pose, nullptr, fused_out, ws, cs, false);
-  if (s == FC_OK && grads) s = enqueue_backward(b, pose, k, upstream, grads, ws, cs);
+  if (fused_out && grads)
+    s = enqueue_query_backward(b, pose, fused_out, k, upstream, grads, ws, cs);
+  else if (fused_out)
+    s = enqueue_forward(b, pose, nullptr, fused_out, ws, cs, false);
+  else
+    s = enqueue_backward(b, pose, k, upstream, grads, ws, cs);
   hipGraph_t graph = nullptr;
   he = hipStreamEndCapture(cs, &graph);
   (void)hipStreamDestroy(cs);

@@ -155,10 +155,24 @@ struct BwdArgs {
   float2* vert_part;  // per chunk [3][n_v]
 };
 
+// The forward's binning and reduction inputs, added to BwdArgs by the
+// one-pass query + adjoint (contacts and penalty gradients from one gather).
+struct QueryExtra {
+  float dirs[3 * FC_MAX_BINS];  // [3][K]
+  const BinCell* bin_lut;       // [kLutCells]
+  int K;
+  float margin;
+  unsigned long long* keys;  // [n_env][K], as FwdArgs::keys
+};
+
 // launch wrappers (fc_kernels.hip)
 hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent, int xcd,
                           int grid, bool from_cand, hipStream_t s);
 hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s);
+// one pass: k_query_backward, then the payload (`payload` holds the contact
+// outputs and keys) and the adjoint's combine
+hipError_t launch_query_backward(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,
+                                 hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int elem, int layout, int nx, int ny, int nz, int bx, int by,
                             int bz, hipStream_t s);

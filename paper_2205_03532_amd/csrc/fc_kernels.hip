@@ -19,7 +19,7 @@
 // flops), so there is no MFMA here: the design work is in the gather
 // (coalesced SoA vertex reads, corner pairs loaded as one 8-byte access,
 // optional brick layout keeping a cell's corners in one 128-byte line) and in
-// keeping the reduction on chip (wave ballot / butterfly max, LDS atomics,
+// keeping the reduction on chip (LDS 64-bit atomic max per bin,
 // one global 64-bit atomicMax per bin per work item).
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -286,53 +286,17 @@ constexpr int kDppHalfMirror = 0x141; // lane i <- lane 7-i within each 8 lanes
 constexpr int kDppMirror = 0x140;     // lane i <- lane 15-i within each row
 
 template <int CTRL>
-__device__ __forceinline__ unsigned dpp_u(unsigned v) {
-  return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
-  return a > b ? a : b;
-}
-template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp_max64(unsigned long long v) {
-  const unsigned lo = dpp_u<CTRL>((unsigned)v), hi = dpp_u<CTRL>((unsigned)(v >> 32));
-  return umax64(v, ((unsigned long long)hi << 32) | lo);
-}
-__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-// max over all 64 lanes; the result is wave-uniform
-__device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
-  v = dpp_max64<kDppXor1>(v);
-  v = dpp_max64<kDppXor2>(v);
-  v = dpp_max64<kDppHalfMirror>(v);
-  v = dpp_max64<kDppMirror>(v);
-  return umax64(umax64(readlane64(v, 0), readlane64(v, 16)), umax64(readlane64(v, 32), readlane64(v, 48)));
-}
-
-// Per-bin max over the candidate lanes of a wavefront: one iteration per
-// distinct bin present (ballot picks the bin, a DPP reduction takes the
-// 64-bit max), then one LDS atomicMax by the bin's leader lane.
-__device__ __forceinline__ void wave_bin_max(bool cand, int bin, unsigned long long key,
-                                             unsigned long long* s_keys) {
-  unsigned long long active = __ballot(cand);
-  const int lane = __lane_id();
-  while (active) {
-    const int leader = __ffsll((long long)active) - 1;
-    const int lb = __builtin_amdgcn_readlane(bin, leader);
-    const bool mine = cand && (bin == lb);
-    const unsigned long long m = __ballot(mine);
-    unsigned long long v = mine ? key : 0ull;
-    if (__popcll(m) > 1) v = wave_max64(v);
-    if (lane == leader) atomicMax(&s_keys[lb], v);
-    active &= ~m;
-  }
+// Per-bin max over a work item: every candidate lane applies its key to the
+// bin's LDS slot with a 64-bit atomic max (ds_max_u64).  Lanes of one
+// wavefront that hit the same bin are serialised by the LDS unit, not by
+// VALU work; the thread-surface patches of one wavefront span many bins, so
+// a per-bin wavefront reduction (one ballot/DPP round per distinct bin) costs
+// more than it saves.  The max is order-independent: the result is exact.
+__device__ __forceinline__ void bin_max(bool cand, int bin, unsigned long long key, unsigned long long* s_keys) {
+  if (cand) atomicMax(&s_keys[bin], key);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,7 +353,7 @@ __device__ __forceinline__ void query_item(const FwdArgs& A, const Item& it, uns
       A.c_nrm[2 * A.Q + q] = nz;
       A.c_bin[q] = (int16_t)bin;
     }
-    if (fused) wave_bin_max(cand, bin, make_key(-phi, (unsigned)v), s_keys);
+    if (fused) bin_max(cand, bin, make_key(-phi, (unsigned)v), s_keys);
   }
 }
 
@@ -414,7 +378,7 @@ __device__ __forceinline__ void reduce_item(const FwdArgs& A, const Item& it, un
   for (int j = 0; j < VPT; ++j) {
     const int v = it.vstart + j * BLOCK + tid;
     const bool cand = (b[j] >= 0) & (b[j] < A.K);  // bins come from caller memory: stay inside s_keys
-    wave_bin_max(cand, b[j], make_key(-phi[j], (unsigned)v), s_keys);
+    bin_max(cand, b[j], make_key(-phi[j], (unsigned)v), s_keys);
   }
 }
 
@@ -602,26 +566,66 @@ template <int CTRL>
 __device__ __forceinline__ float2 dpp_pair(float2 a) {
   return make_float2(dpp_f<CTRL>(a.x), dpp_f<CTRL>(a.y));
 }
-__device__ __forceinline__ float2 readlane_pair(float2 a, int lane) {
-  return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.x), lane)),
-                     __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.y), lane)));
+template <int PATTERN>
+__device__ __forceinline__ float2 swizzle_pair(float2 a) {
+  return make_float2(__int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(a.x), PATTERN)),
+                     __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(a.y), PATTERN)));
+}
+__device__ __forceinline__ float2 xor32_pair(float2 a) {
+  const int addr = (__lane_id() ^ 32) << 2;
+  return make_float2(__int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(a.x))),
+                     __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(a.y))));
+}
+constexpr int kSwzXor16 = 0x401F;  // ds_swizzle bit mode: lane i <- lane i ^ 16 within 32
+
+__device__ __forceinline__ float2 pick(bool hi, float2 a, float2 b) { return hi ? b : a; }
+
+// Which of the eight pairs lane l holds after wave_sum8:
+// (b2^b3) + 2 (b1^b2) + 4 (b0^b2) for the lane's bits b0..b3.
+__device__ __forceinline__ int wave_sum8_slot(int lane) {
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  return (b2 ^ b3) + 2 * (b1 ^ b2) + 4 * (b0 ^ b2);
 }
 
-// Compensated sum of a (sum, compensation) pair over the 64 lanes, in a fixed
-// order (quad, half-row, row, then rows 0..3); wave-uniform result.
-__device__ __forceinline__ float2 wave_sum_pair(float2 a) {
-  a = ncombine(a, dpp_pair<kDppXor1>(a));
-  a = ncombine(a, dpp_pair<kDppXor2>(a));
-  a = ncombine(a, dpp_pair<kDppHalfMirror>(a));
-  a = ncombine(a, dpp_pair<kDppMirror>(a));
-  float2 r = readlane_pair(a, 0);
-  r = ncombine(r, readlane_pair(a, 16));
-  r = ncombine(r, readlane_pair(a, 32));
-  return ncombine(r, readlane_pair(a, 48));
+// Compensated sums of eight (sum, compensation) pairs over the 64 lanes of a
+// wavefront, in a fixed order, by a transposed butterfly.  In each of the
+// first three steps a lane keeps half of its remaining pairs and trades the
+// other half with a partner lane (xor 1 and xor 2 within a quad, then the
+// mirror within eight lanes), so the pairs per lane halve while the lanes each
+// pair covers double; the row mirror, xor 16 and xor 32 then finish the one
+// pair left.  The keep/send choices (b0^b2, b1^b2, b2^b3) are invariant under
+// every later pairing, so both partners always hold the same pair.  Returns
+// the wavefront total of pair wave_sum8_slot(lane); each total sits in eight
+// lanes.  About a quarter of the work of one 64-lane tree per pair.
+__device__ __forceinline__ float2 wave_sum8(const float2 a[8]) {
+  const int lane = __lane_id();
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  const bool s1 = b0 ^ b2, s2 = b1 ^ b2, s3 = b2 ^ b3;
+  float2 x1[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    x1[i] = ncombine(pick(s1, a[i], a[i + 4]), dpp_pair<kDppXor1>(pick(s1, a[i + 4], a[i])));
+  float2 x2[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    x2[i] = ncombine(pick(s2, x1[i], x1[i + 2]), dpp_pair<kDppXor2>(pick(s2, x1[i + 2], x1[i])));
+  float2 x = ncombine(pick(s3, x2[0], x2[1]), dpp_pair<kDppHalfMirror>(pick(s3, x2[1], x2[0])));
+  x = ncombine(x, dpp_pair<kDppMirror>(x));
+  x = ncombine(x, swizzle_pair<kSwzXor16>(x));
+  return ncombine(x, xor32_pair(x));
 }
 
-template <int DT, int LAYOUT>
-__global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
+struct NoQuery {};
+
+// One backward work item: a tile of kBwdTile vertices of one mesh against the
+// envs of one chunk.  With QX = QueryExtra the same pass also forms the
+// forward's candidates and per-bin maxima (one gather serves both): each
+// wavefront keeps its own K keys in LDS, flushed to the env's global keys
+// after every env.
+template <int DT, int LAYOUT, class QX>
+__device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, unsigned long long* s_wkeys,
+                                              const BinCell* s_lut, const float4* s_dir4) {
+  constexpr bool QUERY = !__is_same(QX, NoQuery);
   constexpr int V = kBwdTile / kBwdBlock;
   constexpr int NW = kBwdBlock / 64;
   int idx = blockIdx.x;
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
     const int e = A.env_list[ch.first + c];
     const Rigid P = load_pose(A.pose, A.n_env, e);
     const float up = A.upstream ? A.upstream[e] : 1.f;
-    float2 acc[7];
+    float2 acc[8];
 #pragma unroll
     for (int i = 0; i < 7; ++i) acc[i] = make_float2(0.f, 0.f);
     bool any = false;
@@ -674,6 +678,14 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
     for (int j = 0; j < V; ++j) {
       float phi, gx, gy, gz;
       trilinear(cc[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
+      if constexpr (QUERY) {  // the forward's candidate, bin and per-bin max, as in query_item
+        if (ok[j] & cl[j].inside & (phi < F.margin)) {
+          float nx, ny, nz;
+          normalize(gx, gy, gz, nx, ny, nz);
+          const int bin = argmax_bin_lut(s_lut, s_dir4, F.dirs, F.K, nx, ny, nz);
+          atomicMax(&s_wkeys[bin], make_key(-phi, (unsigned)(it.vstart + j * kBwdBlock + tid)));
+        }
+      }
       const bool act = ok[j] & cl[j].inside & (phi < 0.f);
       float dvx = 0.f, dvy = 0.f, dvz = 0.f;
       if (act) {
@@ -708,23 +720,26 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
         A.d_verts[2 * A.Q + q] = dvz;
       }
     }
-    // fixed-shape reduction within the wavefront (DPP rows, then rows in
-    // order); one partial row per (env, tile, wave), no workgroup barrier
-    float2 red[7];
+    if constexpr (QUERY) {
+      // The wavefront's LDS atomics precede these reads in its own DS
+      // instruction stream, which the LDS executes in order.
+      if (lane < F.K) {
+        const unsigned long long kk = s_wkeys[lane];
+        if (kk) {
+          atomicMax(&F.keys[(long long)e * F.K + lane], kk);
+          s_wkeys[lane] = 0ull;
+        }
+      }
+    }
+    // fixed-shape reduction within the wavefront; one partial row of eight
+    // pairs (the last one zero) per (env, tile, wave), no workgroup barrier
+    float2 red = make_float2(0.f, 0.f);
     if (__ballot(any) != 0ull) {
-#pragma unroll
-      for (int i = 0; i < 7; ++i) red[i] = wave_sum_pair(acc[i]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 7; ++i) red[i] = make_float2(0.f, 0.f);
+      acc[7] = make_float2(0.f, 0.f);
+      red = wave_sum8(acc);
     }
-    if (lane < 7) {
-      float2 r = red[0];
-#pragma unroll
-      for (int i = 1; i < 7; ++i)
-        if (lane == i) r = red[i];
-      A.pose_part[((long long)(A.env_tile_base[e] + it.tile_in_mesh) * NW + wave) * 8 + lane] = r;
-    }
+    if (lane < 8)
+      A.pose_part[((long long)(A.env_tile_base[e] + it.tile_in_mesh) * NW + wave) * 8 + wave_sum8_slot(lane)] = red;
   }
 
   if (shared_v) {
@@ -739,13 +754,38 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
       A.vert_part[base + 2 * (long long)n + v] = accv[j][2];
     }
   }
+}
 
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
+  backward_item<DT, LAYOUT>(A, NoQuery{}, nullptr, nullptr, nullptr);
+}
+
+// Query and adjoint in one pass: the bin-search tables go to LDS as in
+// k_forward, plus K keys per wavefront.
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(kBwdBlock) void k_query_backward(BwdArgs A, QueryExtra F) {
+  __shared__ BinCell s_lut[kLutCells];
+  __shared__ float4 s_dir4[FC_MAX_BINS];
+  __shared__ unsigned long long s_keys[kBwdBlock / 64][FC_MAX_BINS];
+  static_assert(sizeof(BinCell) == sizeof(uint4), "BinCell is one 16-byte load");
+  static_assert(FC_MAX_BINS == 64, "one key slot per lane");
+  const uint4* src = reinterpret_cast<const uint4*>(F.bin_lut);
+  uint4* dst = reinterpret_cast<uint4*>(s_lut);
+  for (int i = threadIdx.x; i < kLutCells; i += kBwdBlock) dst[i] = src[i];
+  if (threadIdx.x < FC_MAX_BINS) {
+    const int k = threadIdx.x < F.K ? threadIdx.x : 0;
+    s_dir4[threadIdx.x] = make_float4(F.dirs[k], F.dirs[F.K + k], F.dirs[2 * F.K + k], 0.f);
+  }
+  s_keys[threadIdx.x >> 6][threadIdx.x & 63] = 0ull;
+  __syncthreads();
+  backward_item<DT, LAYOUT>(A, F, s_keys[threadIdx.x >> 6], s_lut, s_dir4);
 }
 
 // Fixed-order combine of the adjoint's partial sums.  Workgroups
 // [0, pose_blocks) take one environment per wavefront: lane l sums the env's
 // partial rows l, l + 64, ... in order, then the lanes are combined by the
-// fixed DPP tree.  The remaining workgroups take one (component, vertex) per
+// fixed butterfly of wave_sum8.  The remaining workgroups take one (component, vertex) per
 // thread and sum the chunks in order, loads issued eight at a time.
 constexpr int kCombineBatch = 8;
 
@@ -758,23 +798,22 @@ __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, lo
     const int lane = threadIdx.x & 63;
     const int n_rows = A.mesh_tiles[A.envs[e].gm >> 8] * NW;  // (tile, wave) rows in order
     const float2* base = A.pose_part + (long long)A.env_tile_base[e] * NW * 8;
-    float2 acc[7];
+    float2 acc[8];
 #pragma unroll
-    for (int v = 0; v < 7; ++v) acc[v] = make_float2(0.f, 0.f);
+    for (int v = 0; v < 8; ++v) acc[v] = make_float2(0.f, 0.f);
     for (int r = lane; r < n_rows; r += 64) {
       const float2* row = base + (long long)r * 8;
 #pragma unroll
       for (int v = 0; v < 7; ++v) acc[v] = ncombine(acc[v], row[v]);
     }
-    float2 tot[7];
-#pragma unroll
-    for (int v = 0; v < 7; ++v) tot[v] = wave_sum_pair(acc[v]);
-    if (lane == 0) {
-      if (A.loss) A.loss[e] = tot[0].x + tot[0].y;
-      if (A.d_pose) {
+    const float2 tot = wave_sum8(acc);
+    const int v = wave_sum8_slot(lane);
+    if (lane < 8) {
+      if (v == 0) {
+        if (A.loss) A.loss[e] = tot.x + tot.y;
+      } else if (v < 7 && A.d_pose) {
         const float up = A.upstream ? A.upstream[e] : 1.f;
-#pragma unroll
-        for (int v = 1; v < 7; ++v) A.d_pose[(long long)(v - 1) * A.n_env + e] = up * (tot[v].x + tot[v].y);
+        A.d_pose[(long long)(v - 1) * A.n_env + e] = up * (tot.x + tot.y);
       }
     }
     return;
@@ -879,12 +918,9 @@ hipError_t fwd_layout(const FwdArgs& a, int layout, int block, int vpt, int pers
   return fwd_block<DT, FC_LAYOUT_LINEAR>(a, block, vpt, persistent, xcd, grid, from_cand, s);
 }
 
-template <int DT, int LAYOUT>
-hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
-  const int grid = a.xcd ? kXcds * ((a.n_items + kXcds - 1) / kXcds) : a.n_items;
-  hipLaunchKernelGGL((k_backward<DT, LAYOUT>), dim3(grid), dim3(kBwdBlock), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+int bwd_grid(const BwdArgs& a) { return a.xcd ? kXcds * ((a.n_items + kXcds - 1) / kXcds) : a.n_items; }
+
+hipError_t combine_launch(const BwdArgs& a, hipStream_t s) {
   const int shared_v = (a.d_verts != nullptr) && !a.per_env;
   long long nv = 0;
   for (int m = 0; m < a.n_meshes; ++m) nv += a.meshes[m].n;
@@ -893,6 +929,32 @@ hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)(pose_blocks + vert_blocks)), dim3(256), 0, s, a, shared_v, nv,
                      pose_blocks);
   return hipGetLastError();
+}
+
+template <int DT, int LAYOUT>
+hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_backward<DT, LAYOUT>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return combine_launch(a, s);
+}
+
+template <int DT, int LAYOUT>
+hipError_t qbwd_launch(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, hipStream_t s) {
+  hipLaunchKernelGGL((k_query_backward<DT, LAYOUT>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a, q);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_payload<DT, LAYOUT>), dim3((f.n_env + 3) / 4), dim3(256), 0, s, f, 0);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return combine_launch(a, s);
+}
+
+template <int DT>
+hipError_t qbwd_layout(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, int layout, hipStream_t s) {
+  if (layout == FC_LAYOUT_BRICK) return qbwd_launch<DT, FC_LAYOUT_BRICK>(a, q, f, s);
+  if (layout == FC_LAYOUT_SLAB) return qbwd_launch<DT, FC_LAYOUT_SLAB>(a, q, f, s);
+  return qbwd_launch<DT, FC_LAYOUT_LINEAR>(a, q, f, s);
 }
 
 template <int DT>
@@ -933,6 +995,17 @@ hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, in
 hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   return bwd_dtype(a, dtype, layout, s);
+}
+
+hipError_t launch_query_backward(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,
+                                 hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  switch (dtype) {
+    case kF32: return qbwd_layout<kF32>(a, q, payload, layout, s);
+    case kF16: return qbwd_layout<kF16>(a, q, payload, layout, s);
+    case kBF16: return qbwd_layout<kBF16>(a, q, payload, layout, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {

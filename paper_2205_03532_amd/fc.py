@@ -5,7 +5,8 @@ PyTorch supplies device memory (tensors) and the current stream.  The module
 fails loudly when the library is not built; there is no CPU fallback.
 
 Names follow the C ABI: ``fc_sdf_query``, ``fc_contact_reduce``,
-``fc_sdf_query_backward``, ``fc_graph_create`` / ``fc_graph_launch``,
+``fc_sdf_query_backward``, ``fc_sdf_query_and_backward`` (both in one pass),
+``fc_graph_create`` / ``fc_graph_launch``,
 ``fc_grid_to_bricks``, ``fc_autotune_load``.  ``Batch`` owns the device copies
 of a workload's grids and meshes and the opaque ``fc_batch`` handle.
 """
@@ -16,7 +17,9 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfactory_sdf.so")
+# the in-tree build; FC_LIB_PATH selects another build of the same sources
+LIB_PATH = os.environ.get("FC_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                         "libfactory_sdf.so")
 
 FC_OK, FC_ERR_NULL, FC_ERR_SHAPE, FC_ERR_DTYPE, FC_ERR_RANGE, FC_ERR_WORKSPACE, FC_ERR_HIP, FC_ERR_UNSUPPORTED = range(8)
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -75,6 +78,8 @@ SIGNATURES = {
                                     C.c_void_p, C.c_size_t, C.c_void_p]),
     "fc_sdf_query_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.POINTER(fc_grads),
                                         C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fc_sdf_query_and_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_contacts), C.c_float, C.c_void_p,
+                                            C.POINTER(fc_grads), C.c_void_p, C.c_size_t, C.c_void_p]),
     "fc_graph_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_contacts), C.c_float, C.c_void_p,
                                   C.POINTER(fc_grads), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
     "fc_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -299,6 +304,13 @@ def fc_sdf_query_backward(batch: Batch, pose, k, grads, upstream=None, stream=No
     _check(lib().fc_sdf_query_backward(batch.handle, _ptr(pose), float(k), _ptr(upstream),
                                        C.byref(_grads_struct(grads)), C.c_void_p(batch.workspace.data_ptr()),
                                        batch.ws_bytes, _stream(stream)), "fc_sdf_query_backward")
+
+
+def fc_sdf_query_and_backward(batch: Batch, pose, fused_out, k, grads, upstream=None, stream=None):
+    _check(lib().fc_sdf_query_and_backward(batch.handle, _ptr(pose), C.byref(_contacts_struct(fused_out)), float(k),
+                                           _ptr(upstream), C.byref(_grads_struct(grads)),
+                                           C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes,
+                                           _stream(stream)), "fc_sdf_query_and_backward")
 
 
 class Graph:

@@ -30,7 +30,8 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("fc_sdf_query", "fc_contact_reduce", "fc_sdf_query_backward", "fc_graph_create",
+    for required in ("fc_sdf_query", "fc_contact_reduce", "fc_sdf_query_backward", "fc_sdf_query_and_backward",
+                     "fc_graph_create",
                      "fc_workspace_bytes", "fc_autotune_load", "fc_status_str", "fc_last_hip_error"):
         assert required in names
     assert set(names) == set(fc.SIGNATURES), set(names) ^ set(fc.SIGNATURES)
@@ -100,6 +101,7 @@ def test_null_arguments(L):
     assert L.fc_sdf_query(None, None, None, None, None, 0, None) == fc.FC_ERR_NULL
     assert L.fc_contact_reduce(None, None, None, None, None, 0, None) == fc.FC_ERR_NULL
     assert L.fc_sdf_query_backward(None, None, 1.0, None, None, None, 0, None) == fc.FC_ERR_NULL
+    assert L.fc_sdf_query_and_backward(None, None, None, 1.0, None, None, None, 0, None) == fc.FC_ERR_NULL
     assert L.fc_graph_launch(None, None) == fc.FC_ERR_NULL
     assert L.fc_batch_queries(None) == -1
     assert L.fc_workspace_bytes(None) == 0

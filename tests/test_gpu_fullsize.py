@@ -78,3 +78,20 @@ def test_bench_batch_adjoint_repeats_and_matches_subset(full):
     # loss and twist gradients depend only on the env itself
     assert np.array_equal(gs["loss"].cpu().numpy(), a1["loss"][envs])
     assert np.array_equal(gs["d_pose"].cpu().numpy(), a1["d_pose"][:, envs])
+
+
+def test_bench_step_one_pass_equals_separate_calls(full):
+    """The step bench.py times (one fc_sdf_query_and_backward pass) gives the
+    contacts and gradients of the separate calls, bit for bit, at full size."""
+    torch = torch_gpu()
+    w, b, pose = full
+    o1, o2 = b.new_contacts(), b.new_contacts()
+    g1, g2 = b.new_grads(per_env=False), b.new_grads(per_env=False)
+    fc.fc_sdf_query(b, pose, fused_out=o1)
+    fc.fc_sdf_query_backward(b, pose, 1e4, g1)
+    fc.fc_sdf_query_and_backward(b, pose, o2, 1e4, g2)
+    torch.cuda.synchronize()
+    assert_same(to_np(o1), to_np(o2))
+    assert_same(to_np({k: v for k, v in g1.items() if k != "per_env"}),
+                to_np({k: v for k, v in g2.items() if k != "per_env"}))
+    assert int(to_np(o2)["count"].sum()) > 0
