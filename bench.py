@@ -64,13 +64,13 @@ PROFILED_KERNELS = ("k_query_backward", "k_forward", "k_backward")
 
 
 def _median_counter(csv_dir, kernel, counter, required=True):
-    """Median per-dispatch value of `counter` for kernel `kernel` (matched as
-    '::kernel<' in the demangled name, so k_backward does not match
-    k_query_backward)."""
+    """Median per-dispatch value of `counter` for kernel `kernel`: a name of
+    this library's templates is matched as '::kernel<' in the demangled name
+    (so k_backward does not match k_query_backward), any other as a substring."""
     import csv
     import glob
 
-    pat = f"::{kernel}<"
+    pat = f"::{kernel}<" if kernel in PROFILED_KERNELS else kernel
     vals = []
     for path in glob.glob(os.path.join(csv_dir, "*counter_collection.csv")):
         for r in csv.DictReader(open(path)):

@@ -94,51 +94,57 @@ __device__ __forceinline__ Cell locate(const GridDev& g, float x, float y, float
   return c;
 }
 
-// (v[i], v[i+1]) as one unaligned 8-byte (FP32) or 4-byte (FP16/BF16) load
+// (v[0], v[1]) at p as one unaligned 8-byte (FP32) or 4-byte (FP16/BF16) load
 template <int DT>
-__device__ __forceinline__ float2 ld_pair(const void* __restrict__ base, int i);
+__device__ __forceinline__ float2 ld_pair(const void* __restrict__ p);
 
 template <>
-__device__ __forceinline__ float2 ld_pair<kF32>(const void* __restrict__ base, int i) {
+__device__ __forceinline__ float2 ld_pair<kF32>(const void* __restrict__ p) {
   float2 r;
-  __builtin_memcpy(&r, static_cast<const float*>(base) + i, 8);
+  __builtin_memcpy(&r, p, 8);
   return r;
 }
 template <>
-__device__ __forceinline__ float2 ld_pair<kF16>(const void* __restrict__ base, int i) {
+__device__ __forceinline__ float2 ld_pair<kF16>(const void* __restrict__ p) {
   unsigned u;
-  __builtin_memcpy(&u, static_cast<const uint16_t*>(base) + i, 4);
+  __builtin_memcpy(&u, p, 4);
   return make_float2(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))),
                      __half2float(__ushort_as_half((unsigned short)(u >> 16))));
 }
 template <>
-__device__ __forceinline__ float2 ld_pair<kBF16>(const void* __restrict__ base, int i) {
+__device__ __forceinline__ float2 ld_pair<kBF16>(const void* __restrict__ p) {
   unsigned u;
-  __builtin_memcpy(&u, static_cast<const uint16_t*>(base) + i, 4);
+  __builtin_memcpy(&u, p, 4);
   return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
 }
 
 // Corner order: c[a + 2b + 4c] = value at node (ix+a, iy+b, iz+c).
 template <int DT, int LAYOUT>
 __device__ __forceinline__ void gather(const GridDev& g, const Cell& cl, float c[8]) {
-  int i0, sy, sz;
+  // cell indexes are >= 0 and element indexes < 2^31 (checked at batch
+  // creation): unsigned arithmetic, so the divisions need no sign fix-up
+  unsigned i0, sy, sz;
+  const unsigned ix = (unsigned)cl.ix, iy = (unsigned)cl.iy, iz = (unsigned)cl.iz;
   if constexpr (LAYOUT == FC_LAYOUT_LINEAR) {
-    sy = g.nx;
-    sz = g.nx * g.ny;
-    i0 = (cl.iz * g.ny + cl.iy) * g.nx + cl.ix;
+    sy = (unsigned)g.nx;
+    sz = (unsigned)g.nx * (unsigned)g.ny;
+    i0 = (iz * (unsigned)g.ny + iy) * (unsigned)g.nx + ix;
   } else {
     using B = BrickShape<LAYOUT>;
-    constexpr int CX = B::NX - 1, CY = B::NY - 1, CZ = B::NZ - 1;
-    const int bxi = cl.ix / CX, byi = cl.iy / CY, bzi = cl.iz / CZ;
-    const int lx = cl.ix - CX * bxi, ly = cl.iy - CY * byi, lz = cl.iz - CZ * bzi;
+    constexpr unsigned CX = B::NX - 1, CY = B::NY - 1, CZ = B::NZ - 1;
+    const unsigned bxi = ix / CX, byi = iy / CY, bzi = iz / CZ;
+    const unsigned lx = ix - CX * bxi, ly = iy - CY * byi, lz = iz - CZ * bzi;
     sy = B::NX;
     sz = B::NX * B::NY;
-    i0 = ((bzi * g.by + byi) * g.bx + bxi) * (B::NX * B::NY * B::NZ) + (lz * sz + ly * sy + lx);
+    i0 = ((bzi * (unsigned)g.by + byi) * (unsigned)g.bx + bxi) * (B::NX * B::NY * B::NZ) + (lz * sz + ly * sy + lx);
   }
-  const float2 p00 = ld_pair<DT>(g.data, i0);
-  const float2 p10 = ld_pair<DT>(g.data, i0 + sy);
-  const float2 p01 = ld_pair<DT>(g.data, i0 + sz);
-  const float2 p11 = ld_pair<DT>(g.data, i0 + sz + sy);
+  // one 64-bit base per query; the other rows at constant offsets (bricks)
+  constexpr size_t E = DT == kF32 ? 4 : 2;
+  const char* b = static_cast<const char*>(g.data) + (size_t)i0 * E;
+  const float2 p00 = ld_pair<DT>(b);
+  const float2 p10 = ld_pair<DT>(b + (size_t)sy * E);
+  const float2 p01 = ld_pair<DT>(b + (size_t)sz * E);
+  const float2 p11 = ld_pair<DT>(b + (size_t)(sz + sy) * E);
   c[0] = p00.x; c[1] = p00.y;
   c[2] = p10.x; c[3] = p10.y;
   c[4] = p01.x; c[5] = p01.y;
@@ -224,7 +230,9 @@ __device__ __forceinline__ int cube_cell(float nx, float ny, float nz) {
     v = ny;
     m = az;
   }
-  const float s = (0.5f * kLutN) / m;
+  // hardware reciprocal (1 ulp): the table's cones carry a 1e-4 rad margin
+  // for the cell choice, far above this rounding
+  const float s = (0.5f * kLutN) * __builtin_amdgcn_rcpf(m);
   const int iu = min(max((int)floorf(fmaf(u, s, 0.5f * kLutN)), 0), kLutN - 1);
   const int iv = min(max((int)floorf(fmaf(v, s, 0.5f * kLutN)), 0), kLutN - 1);
   return (face * kLutN + iv) * kLutN + iu;
@@ -239,11 +247,12 @@ __device__ __forceinline__ int argmax_bin_lut(const BinCell* __restrict__ lut, c
                                               float nz) {
   if ((nx == 0.f) & (ny == 0.f) & (nz == 0.f)) return 0;
   const BinCell c = lut[cube_cell(nx, ny, nz)];
-  if (c.n == kLutFull) return argmax_bin(dirs, K, nx, ny, nz);
+  const int n = c.n;
+  if (n == kLutFull) return argmax_bin(dirs, K, nx, ny, nz);
   int bin = c.k[0];
   float4 d = dir4[bin];
   float best = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
-  for (int i = 1; i < c.n; ++i) {
+  for (int i = 1; i < n; ++i) {
     const int k = c.k[i];
     d = dir4[k];
     const float v = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
@@ -562,6 +571,14 @@ __device__ __forceinline__ float2 ncombine(float2 a, float2 b) {
   return make_float2(t, (a.y + b.y) + e);
 }
 
+// a + b as an unevaluated (sum, rounding error) pair, exact for finite
+// inputs (Knuth's branch-free TwoSum)
+__device__ __forceinline__ float2 two_sum(float a, float b) {
+  const float s = a + b;
+  const float bb = s - a;
+  return make_float2(s, (a - (s - bb)) + (b - bb));
+}
+
 template <int CTRL>
 __device__ __forceinline__ float2 dpp_pair(float2 a) {
   return make_float2(dpp_f<CTRL>(a.x), dpp_f<CTRL>(a.y));
@@ -627,6 +644,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
                                               const BinCell* s_lut, const float4* s_dir4) {
   constexpr bool QUERY = !__is_same(QX, NoQuery);
   constexpr int V = kBwdTile / kBwdBlock;
+  static_assert(V >= 2, "lane pairs start from two terms");
   constexpr int NW = kBwdBlock / 64;
   int idx = blockIdx.x;
   if (A.xcd) {  // XCD x serves the x-th contiguous range of items (see item_range)
@@ -656,13 +674,24 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
 #pragma unroll
   for (int j = 0; j < V; ++j) accv[j][0] = accv[j][1] = accv[j][2] = make_float2(0.f, 0.f);
 
+  // R, t and the upstream weight of the chunk's envs, computed once per item
+  __shared__ float4 s_pose[kBwdChunk][4];
+  if (tid < ch.len) {
+    const int e = A.env_list[ch.first + tid];
+    const Rigid P = load_pose(A.pose, A.n_env, e);
+    s_pose[tid][0] = make_float4(P.r00, P.r01, P.r02, P.tx);
+    s_pose[tid][1] = make_float4(P.r10, P.r11, P.r12, P.ty);
+    s_pose[tid][2] = make_float4(P.r20, P.r21, P.r22, P.tz);
+    s_pose[tid][3] = make_float4(A.upstream ? A.upstream[e] : 1.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
+
   for (int c = 0; c < ch.len; ++c) {
     const int e = A.env_list[ch.first + c];
-    const Rigid P = load_pose(A.pose, A.n_env, e);
-    const float up = A.upstream ? A.upstream[e] : 1.f;
-    float2 acc[8];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) acc[i] = make_float2(0.f, 0.f);
+    const float4 p0 = s_pose[c][0], p1 = s_pose[c][1], p2 = s_pose[c][2];
+    const Rigid P{p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, p0.w, p1.w, p2.w};
+    const float up = s_pose[c][3].x;
+    float T[V][7];  // this lane's terms of the env's sums (zero where inactive)
     bool any = false;
     float xb[V], yb[V], zb[V];
     Cell cl[V];
@@ -688,6 +717,8 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
       }
       const bool act = ok[j] & cl[j].inside & (phi < 0.f);
       float dvx = 0.f, dvy = 0.f, dvz = 0.f;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) T[j][i] = 0.f;
       if (act) {
         any = true;
         const float kphi = A.k * phi;
@@ -696,13 +727,13 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
         const float mx = fmaf(yb[j], wz, -(zb[j] * wy));
         const float my = fmaf(zb[j], wx, -(xb[j] * wz));
         const float mz = fmaf(xb[j], wy, -(yb[j] * wx));
-        nadd(acc[0], 0.5f * kphi * phi);
-        nadd(acc[1], wx);
-        nadd(acc[2], wy);
-        nadd(acc[3], wz);
-        nadd(acc[4], mx);
-        nadd(acc[5], my);
-        nadd(acc[6], mz);
+        T[j][0] = 0.5f * kphi * phi;
+        T[j][1] = wx;
+        T[j][2] = wy;
+        T[j][3] = wz;
+        T[j][4] = mx;
+        T[j][5] = my;
+        T[j][6] = mz;
         // R^T w, scaled by the upstream gradient
         dvx = up * fmaf(P.r00, wx, fmaf(P.r10, wy, P.r20 * wz));
         dvy = up * fmaf(P.r01, wx, fmaf(P.r11, wy, P.r21 * wz));
@@ -735,6 +766,13 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     // pairs (the last one zero) per (env, tile, wave), no workgroup barrier
     float2 red = make_float2(0.f, 0.f);
     if (__ballot(any) != 0ull) {
+      float2 acc[8];  // the lane's terms, summed exactly as (sum, error) pairs
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        acc[i] = two_sum(T[0][i], T[1][i]);
+#pragma unroll
+        for (int j = 2; j < V; ++j) nadd(acc[i], T[j][i]);
+      }
       acc[7] = make_float2(0.f, 0.f);
       red = wave_sum8(acc);
     }
