@@ -291,6 +291,28 @@ int32_t fc_autotune_load(const char* json_path);
  * cap bytes written). Returns the full length, or -1 for NULL. */
 int32_t fc_batch_signature(const fc_batch* batch, char* buf, int32_t cap);
 
+/* Per-launch timing of the main kernels.  After fc_batch_set_timing(batch, n)
+ * the next n compute calls on this batch (fc_sdf_query, fc_contact_reduce,
+ * fc_sdf_query_backward, fc_sdf_query_and_backward; not graph capture or
+ * replay) record a pair of HIP events on their stream right before and right
+ * after their main kernel, leaving out the small payload / combine kernels
+ * that follow it.  n = 0 turns timing off; 0 <= n <= FC_MAX_TIMING_RECORDS
+ * (else FC_ERR_RANGE).  Creates the events (a host call, not asynchronous;
+ * do it outside timed regions).  For one thread at a time per batch. */
+#define FC_MAX_TIMING_RECORDS 65536
+typedef enum fc_kernel_id {
+  FC_KERNEL_FORWARD = 0,        /* k_forward (any mode) */
+  FC_KERNEL_BACKWARD = 1,       /* k_backward */
+  FC_KERNEL_QUERY_BACKWARD = 2  /* k_query_backward */
+} fc_kernel_id;
+fc_status fc_batch_set_timing(fc_batch* batch, int32_t max_records);
+/* Waits for the recorded launches and writes, for the first min(recorded,
+ * max) of them in call order, the main kernel's duration in milliseconds and
+ * its fc_kernel_id; then starts recording again from the first slot.
+ * Returns the number written, or -1 (NULL arguments, or a HIP error: see
+ * fc_last_hip_error). */
+int32_t fc_batch_read_timing(fc_batch* batch, float* ms, int32_t* kernel, int32_t max);
+
 const char* fc_status_str(fc_status status);
 int32_t fc_last_hip_error(void); /* hipError_t of the last FC_ERR_HIP on this thread */
 const char* fc_version(void);

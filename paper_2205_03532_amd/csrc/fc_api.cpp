@@ -374,6 +374,10 @@ struct fc_batch {
   long long mesh_vpart0[FC_MAX_TYPES] = {0};
   // workspace layout (bytes)
   size_t off_keys = 0, off_workctr = 0, off_pose = 0, off_vert = 0, ws_bytes = 0;
+  // per-launch timing of the main kernels (diagnostics; one thread at a time)
+  std::vector<hipEvent_t> t_ev;     // [2 * slots]: before, after
+  mutable std::vector<int> t_kind;  // [slots]
+  mutable int t_next = 0;
 };
 
 namespace {
@@ -396,6 +400,24 @@ void free_tables(fc_batch* b) {
 }
 
 int gm_of(const fc_batch* b, int e) { return b->env_grid[e] | (b->env_mesh[e] << 8); }
+
+void free_timing(fc_batch* b) {
+  for (hipEvent_t e : b->t_ev)
+    if (e) (void)hipEventDestroy(e);
+  b->t_ev.clear();
+  b->t_kind.clear();
+  b->t_next = 0;
+}
+
+// Events for the main kernel of the call being enqueued, or null when timing
+// is off, its slots are used up, or the call is being captured into a graph.
+const KernelMarks* take_marks(const fc_batch* b, int kind, bool timed, KernelMarks& m) {
+  if (!timed || b->t_next >= (int)b->t_kind.size()) return nullptr;
+  m.before = b->t_ev[2 * b->t_next];
+  m.after = b->t_ev[2 * b->t_next + 1];
+  b->t_kind[b->t_next++] = kind;
+  return &m;
+}
 
 fc_status build_forward_tables(fc_batch* b) {
   std::vector<Item> items;
@@ -583,11 +605,12 @@ bool contacts_ok(const fc_contacts* o) {
 }
 
 fc_status enqueue_forward(const fc_batch* b, const float* pose, const fc_candidates* cand, const fc_contacts* out,
-                          void* ws, hipStream_t s, bool from_cand) {
+                          void* ws, hipStream_t s, bool from_cand, bool timed) {
   const FwdArgs a = make_fwd(b, pose, cand, out, ws);
   const int vpt = b->launch.tile / b->launch.block;
+  KernelMarks m;
   FC_HIP(launch_forward(a, b->dtype, b->layout, b->launch.block, vpt, b->launch.persistent, b->launch.xcd_remap,
-                        forward_grid(b), from_cand, s));
+                        forward_grid(b), from_cand, s, take_marks(b, FC_KERNEL_FORWARD, timed, m)));
   return FC_OK;
 }
 
@@ -626,15 +649,16 @@ BwdArgs make_bwd(const fc_batch* b, const float* pose, float k, const float* ups
 }
 
 fc_status enqueue_backward(const fc_batch* b, const float* pose, float k, const float* upstream, const fc_grads* out,
-                           void* ws, hipStream_t s) {
+                           void* ws, hipStream_t s, bool timed) {
   const BwdArgs a = make_bwd(b, pose, k, upstream, out, ws);
-  FC_HIP(launch_backward(a, b->dtype, b->layout, s));
+  KernelMarks m;
+  FC_HIP(launch_backward(a, b->dtype, b->layout, s, take_marks(b, FC_KERNEL_BACKWARD, timed, m)));
   return FC_OK;
 }
 
 // fused query + reduce and the adjoint, from one gather per query
 fc_status enqueue_query_backward(const fc_batch* b, const float* pose, const fc_contacts* contacts, float k,
-                                 const float* upstream, const fc_grads* out, void* ws, hipStream_t s) {
+                                 const float* upstream, const fc_grads* out, void* ws, hipStream_t s, bool timed) {
   const BwdArgs a = make_bwd(b, pose, k, upstream, out, ws);
   const FwdArgs f = make_fwd(b, pose, nullptr, contacts, ws);
   QueryExtra q;
@@ -644,7 +668,8 @@ fc_status enqueue_query_backward(const fc_batch* b, const float* pose, const fc_
   q.K = b->K;
   q.margin = b->margin;
   q.keys = f.keys;
-  FC_HIP(launch_query_backward(a, q, f, b->dtype, b->layout, s));
+  KernelMarks m;
+  FC_HIP(launch_query_backward(a, q, f, b->dtype, b->layout, s, take_marks(b, FC_KERNEL_QUERY_BACKWARD, timed, m)));
   return FC_OK;
 }
 
@@ -734,7 +759,40 @@ void fc_batch_destroy(fc_batch* b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   free_tables(b);
+  free_timing(b);
   delete b;
+}
+
+fc_status fc_batch_set_timing(fc_batch* b, int32_t max_records) {
+  if (!b) return FC_ERR_NULL;
+  if (max_records < 0 || max_records > FC_MAX_TIMING_RECORDS) return FC_ERR_RANGE;
+  free_timing(b);
+  b->t_ev.assign(2 * (size_t)max_records, nullptr);
+  for (auto& e : b->t_ev) {
+    const hipError_t he = hipEventCreate(&e);
+    if (he != hipSuccess) {
+      free_timing(b);
+      return hip_fail(he);
+    }
+  }
+  b->t_kind.assign(max_records, -1);
+  return FC_OK;
+}
+
+int32_t fc_batch_read_timing(fc_batch* b, float* ms, int32_t* kernel, int32_t max) {
+  if (!b || max < 0 || (max > 0 && (!ms || !kernel))) return -1;
+  const int n = std::min(b->t_next, (int)max);
+  for (int i = 0; i < n; ++i) {
+    hipError_t he = hipEventSynchronize(b->t_ev[2 * i + 1]);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms[i], b->t_ev[2 * i], b->t_ev[2 * i + 1]);
+    if (he != hipSuccess) {
+      (void)hip_fail(he);
+      return -1;
+    }
+    kernel[i] = b->t_kind[i];
+  }
+  b->t_next = 0;
+  return n;
 }
 
 int64_t fc_batch_queries(const fc_batch* b) { return b ? b->Q : -1; }
@@ -785,7 +843,7 @@ fc_status fc_sdf_query(const fc_batch* b, const float* pose, const fc_candidates
   if (fused_out && !contacts_ok(fused_out)) return FC_ERR_NULL;
   fc_status s = check_ws(b, ws, ws_bytes);
   if (s != FC_OK) return s;
-  return enqueue_forward(b, pose, cand, fused_out, ws, (hipStream_t)stream, false);
+  return enqueue_forward(b, pose, cand, fused_out, ws, (hipStream_t)stream, false, true);
 }
 
 fc_status fc_contact_reduce(const fc_batch* b, const float* pose, const fc_candidates* cand, const fc_contacts* out,
@@ -794,14 +852,14 @@ fc_status fc_contact_reduce(const fc_batch* b, const float* pose, const fc_candi
   if (!cand->phi || !cand->normal || !cand->bin || !contacts_ok(out)) return FC_ERR_NULL;
   fc_status s = check_ws(b, ws, ws_bytes);
   if (s != FC_OK) return s;
-  return enqueue_forward(b, pose, cand, out, ws, (hipStream_t)stream, true);
+  return enqueue_forward(b, pose, cand, out, ws, (hipStream_t)stream, true, true);
 }
 
 fc_status fc_sdf_query_backward(const fc_batch* b, const float* pose, float k, const float* upstream,
                                 const fc_grads* out, void* ws, size_t ws_bytes, void* stream) {
   fc_status s = validate_backward(b, pose, k, out, ws, ws_bytes);
   if (s != FC_OK) return s;
-  return enqueue_backward(b, pose, k, upstream, out, ws, (hipStream_t)stream);
+  return enqueue_backward(b, pose, k, upstream, out, ws, (hipStream_t)stream, true);
 }
 
 fc_status fc_sdf_query_and_backward(const fc_batch* b, const float* pose, const fc_contacts* fused_out, float k,
@@ -811,7 +869,7 @@ fc_status fc_sdf_query_and_backward(const fc_batch* b, const float* pose, const 
   if (!contacts_ok(fused_out)) return FC_ERR_NULL;
   fc_status s = validate_backward(b, pose, k, grads, ws, ws_bytes);
   if (s != FC_OK) return s;
-  return enqueue_query_backward(b, pose, fused_out, k, upstream, grads, ws, (hipStream_t)stream);
+  return enqueue_query_backward(b, pose, fused_out, k, upstream, grads, ws, (hipStream_t)stream, true);
 }
 
 struct fc_graph {
@@ -839,11 +897,11 @@ fc_status fc_graph_create(const fc_batch* b, const float* pose, const fc_contact
     return hip_fail(he);
   }
   if (fused_out && grads)
-    s = enqueue_query_backward(b, pose, fused_out, k, upstream, grads, ws, cs);
+    s = enqueue_query_backward(b, pose, fused_out, k, upstream, grads, ws, cs, false);
   else if (fused_out)
-    s = enqueue_forward(b, pose, nullptr, fused_out, ws, cs, false);
+    s = enqueue_forward(b, pose, nullptr, fused_out, ws, cs, false, false);
   else
-    s = enqueue_backward(b, pose, k, upstream, grads, ws, cs);
+    s = enqueue_backward(b, pose, k, upstream, grads, ws, cs, false);
   hipGraph_t graph = nullptr;
   he = hipStreamEndCapture(cs, &graph);
   (void)hipStreamDestroy(cs);

@@ -165,14 +165,22 @@ struct QueryExtra {
   unsigned long long* keys;  // [n_env][K], as FwdArgs::keys
 };
 
+// HIP events (hipEvent_t) recorded on the launch stream right before and right
+// after the main kernel of a launch (k_forward, k_backward, k_query_backward),
+// not around its small companion kernels; null pointer = no events.
+struct KernelMarks {
+  void* before;
+  void* after;
+};
+
 // launch wrappers (fc_kernels.hip)
 hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent, int xcd,
-                          int grid, bool from_cand, hipStream_t s);
-hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s);
+                          int grid, bool from_cand, hipStream_t s, const KernelMarks* m);
+hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m);
 // one pass: k_query_backward, then the payload (`payload` holds the contact
 // outputs and keys) and the adjoint's combine
 hipError_t launch_query_backward(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,
-                                 hipStream_t s);
+                                 hipStream_t s, const KernelMarks* m);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int elem, int layout, int nx, int ny, int nz, int bx, int by,
                             int bz, hipStream_t s);

@@ -284,10 +284,10 @@ __device__ __forceinline__ float key_depth(unsigned long long key) {
 __device__ __forceinline__ unsigned key_vidx(unsigned long long key) { return 0xFFFFFFFFu - (unsigned)key; }
 
 // ---------------------------------------------------------------------------
-// wavefront reductions with DPP row permutations (register-to-register, no
-// LDS traffic): xor-1 and xor-2 quad permutes, then the half-row and row
-// mirrors complete each 16-lane row; the four row results are read with
-// readlane and combined in row order.  Needs all 64 lanes active.
+// DPP lane permutations (register to register) for the adjoint's wavefront
+// reduction (wave_sum8): xor-1 and xor-2 quad permutes and the half-row and
+// row mirrors; lanes 16 and 32 apart are reached through ds_swizzle and
+// ds_bpermute.  All 64 lanes must be active.
 // ---------------------------------------------------------------------------
 constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
@@ -911,11 +911,30 @@ __global__ void k_to_bricks(const T* __restrict__ src, T* __restrict__ dst, int 
   }
 }
 
+// Optional HIP events around the main kernel of the launch in progress (set
+// by the launch_* entry points for the calling thread; see KernelMarks).
+thread_local const KernelMarks* t_marks = nullptr;
+
+struct MarksScope {
+  explicit MarksScope(const KernelMarks* m) { t_marks = m; }
+  ~MarksScope() { t_marks = nullptr; }
+};
+
+hipError_t mark(bool after, hipStream_t s) {
+  if (!t_marks) return hipSuccess;
+  return hipEventRecord(after ? static_cast<hipEvent_t>(t_marks->after) : static_cast<hipEvent_t>(t_marks->before),
+                        s);
+}
+
 template <int DT, int LAYOUT, int BLOCK, int VPT>
 hipError_t fwd_launch(const FwdArgs& a, int persistent, int xcd, int grid, bool from_cand, hipStream_t s) {
+  hipError_t e = mark(false, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_forward<DT, LAYOUT, BLOCK, VPT>), dim3(grid), dim3(BLOCK), 0, s, a, persistent,
                      from_cand ? 1 : 0, xcd);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = mark(true, s);
   if (e != hipSuccess) return e;
   if (a.o_vidx) {
     hipLaunchKernelGGL((k_payload<DT, LAYOUT>), dim3((a.n_env + 3) / 4), dim3(256), 0, s, a, from_cand ? 1 : 0);
@@ -971,16 +990,24 @@ hipError_t combine_launch(const BwdArgs& a, hipStream_t s) {
 
 template <int DT, int LAYOUT>
 hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
+  hipError_t e = mark(false, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_backward<DT, LAYOUT>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a);
-  const hipError_t e = hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = mark(true, s);
   if (e != hipSuccess) return e;
   return combine_launch(a, s);
 }
 
 template <int DT, int LAYOUT>
 hipError_t qbwd_launch(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, hipStream_t s) {
+  hipError_t e = mark(false, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_query_backward<DT, LAYOUT>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a, q);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = mark(true, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_payload<DT, LAYOUT>), dim3((f.n_env + 3) / 4), dim3(256), 0, s, f, 0);
   e = hipGetLastError();
@@ -1018,8 +1045,9 @@ bool forward_shape_supported(int block, int vpt) {
 }
 
 hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent, int xcd,
-                          int grid, bool from_cand, hipStream_t s) {
+                          int grid, bool from_cand, hipStream_t s, const KernelMarks* m) {
   if (grid <= 0) return hipSuccess;
+  const MarksScope scope(m);
   // the reduction-from-candidates pass never reads the grid: one instantiation serves every dtype
   if (from_cand) return fwd_layout<kF32>(a, FC_LAYOUT_LINEAR, block, vpt, persistent, xcd, grid, true, s);
   switch (dtype) {
@@ -1030,14 +1058,16 @@ hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, in
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s) {
+hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m) {
   if (a.n_items <= 0) return hipSuccess;
+  const MarksScope scope(m);
   return bwd_dtype(a, dtype, layout, s);
 }
 
 hipError_t launch_query_backward(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,
-                                 hipStream_t s) {
+                                 hipStream_t s, const KernelMarks* m) {
   if (a.n_items <= 0) return hipSuccess;
+  const MarksScope scope(m);
   switch (dtype) {
     case kF32: return qbwd_layout<kF32>(a, q, payload, layout, s);
     case kF16: return qbwd_layout<kF16>(a, q, payload, layout, s);

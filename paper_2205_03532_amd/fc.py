@@ -17,6 +17,8 @@ import os
 
 import numpy as np
 
+FC_KERNEL_FORWARD, FC_KERNEL_BACKWARD, FC_KERNEL_QUERY_BACKWARD = 0, 1, 2
+
 # the in-tree build; FC_LIB_PATH selects another build of the same sources
 LIB_PATH = os.environ.get("FC_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                          "libfactory_sdf.so")
@@ -89,6 +91,8 @@ SIGNATURES = {
                                     C.c_void_p]),
     "fc_autotune_load": (C.c_int32, [C.c_char_p]),
     "fc_batch_signature": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32]),
+    "fc_batch_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fc_batch_read_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32]),
     "fc_status_str": (C.c_char_p, [C.c_int]),
     "fc_last_hip_error": (C.c_int32, []),
     "fc_version": (C.c_char_p, []),
@@ -248,6 +252,21 @@ class Batch:
                     d_pose=torch.empty(6, self.n_env, dtype=torch.float32, device=self.device) if d_pose else None,
                     d_verts=(torch.empty(3 * nv, dtype=torch.float32, device=self.device) if d_verts else None),
                     per_env=bool(per_env))
+
+    def set_timing(self, max_records):
+        """Record the main kernel's duration for the next max_records calls (0: off)."""
+        _check(lib().fc_batch_set_timing(self.handle, int(max_records)), "fc_batch_set_timing")
+        self._timing_cap = int(max_records)
+
+    def read_timing(self):
+        """(durations in ms, kernel ids) of the calls recorded since set_timing or the last read."""
+        cap = max(getattr(self, "_timing_cap", 0), 1)
+        ms = (C.c_float * cap)()
+        kid = (C.c_int32 * cap)()
+        n = lib().fc_batch_read_timing(self.handle, ms, kid, cap)
+        if n < 0:
+            raise RuntimeError(f"fc_batch_read_timing failed (hip error {lib().fc_last_hip_error()})")
+        return np.array(ms[:n], dtype=np.float64), np.array(kid[:n], dtype=np.int32)
 
     def set_launch(self, block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=0):
         _check(lib().fc_batch_set_launch(self.handle, C.byref(fc_launch(block, tile, persistent, grid_mult,

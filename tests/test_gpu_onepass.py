@@ -146,3 +146,32 @@ def test_graph_of_both_equals_eager():
         assert_same(ref_o, to_np(o))
         assert_same(ref_g, to_np({k: v for k, v in g.items() if k != "per_env"}))
         separate(b, pose)  # eager work between replays
+
+
+def test_kernel_timing_records_main_kernels_only():
+    """fc_batch_set_timing records one event pair per compute call, in call
+    order with the kernel ids; graph replays are not recorded."""
+    torch = torch_gpu()
+    w = W.subset(W.torus_workload(), range(16))
+    b = fc.Batch.from_workload(w)
+    pose = fc.pose_tensor(w.pose)
+    o = b.new_contacts()
+    g = b.new_grads()
+    b.set_timing(8)
+    fc.fc_sdf_query_and_backward(b, pose, o, KP, g)
+    fc.fc_sdf_query(b, pose, fused_out=o)
+    fc.fc_sdf_query_backward(b, pose, KP, g)
+    ms, kid = b.read_timing()
+    assert list(kid) == [fc.FC_KERNEL_QUERY_BACKWARD, fc.FC_KERNEL_FORWARD, fc.FC_KERNEL_BACKWARD]
+    assert np.all(ms > 0) and np.all(ms < 1e3)
+    graph = fc.fc_graph_create(b, pose, fused_out=o, k=KP, grads=g)
+    graph.launch()
+    torch.cuda.synchronize()
+    assert len(b.read_timing()[0]) == 0  # capture and replay record nothing
+    for _ in range(10):  # more calls than slots: the first 8 are kept
+        fc.fc_sdf_query(b, pose, fused_out=o)
+    ms, kid = b.read_timing()
+    assert len(ms) == 8 and set(kid) == {fc.FC_KERNEL_FORWARD}
+    b.set_timing(0)
+    fc.fc_sdf_query(b, pose, fused_out=o)
+    assert len(b.read_timing()[0]) == 0
