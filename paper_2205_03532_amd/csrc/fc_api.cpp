@@ -354,6 +354,7 @@ struct fc_batch {
   long long Q = 0;
   fc_launch launch{256, 1024, 0, 8, 0};
   int num_cus = 256;
+  int bwd_chunk = 0;  // envs per backward item (choose_bwd_chunk)
   std::string signature;
   // forward tables
   BinCell* d_lut = nullptr;
@@ -450,6 +451,24 @@ fc_status build_forward_tables(fc_batch* b) {
   return upload(&b->d_envs, envs);
 }
 
+// Envs per backward item.  Each item keeps its vertices' gradient sums in
+// registers across the chunk's envs, so the fewer items the less partial-sum
+// traffic; but a grid larger than what the device holds resident at once
+// runs a second round whose few workgroups idle the rest of the chip.  The
+// chunk is the smallest in [kBwdChunkMin, kBwdChunkMax] whose items fit in
+// one resident round (or kBwdChunkMax when none does).
+int choose_bwd_chunk(const fc_batch* b, const std::vector<std::vector<int>>& groups, int capacity) {
+  for (int c = kBwdChunkMin; c <= kBwdChunkMax; ++c) {
+    long long items = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const int m = (int)(gi / b->grids.size());
+      items += (long long)ceil_div((int)groups[gi].size(), c) * b->mesh_tiles[m];
+    }
+    if (items <= capacity) return c;
+  }
+  return kBwdChunkMax;
+}
+
 fc_status build_backward_tables(fc_batch* b) {
   const int nm = (int)b->meshes.size();
   std::vector<int> env_list;
@@ -468,6 +487,14 @@ fc_status build_backward_tables(fc_batch* b) {
     rows += b->mesh_tiles[b->env_mesh[e]];
   }
   // chunks: grouped by mesh, then grid, then env order
+  const int ng = (int)b->grids.size();
+  std::vector<std::vector<int>> groups((size_t)nm * ng);
+  for (int oi = 0; oi < b->n_env; ++oi) {
+    const int e = b->order[oi];
+    groups[(size_t)b->env_mesh[e] * ng + b->env_grid[e]].push_back(e);
+  }
+  b->bwd_chunk = choose_bwd_chunk(b, groups, b->num_cus * backward_blocks_per_cu(b->dtype, b->layout));
+  const size_t chunk = (size_t)b->bwd_chunk;
   long long vpart = 0;
   long long voff = 0;
   for (int m = 0; m < nm; ++m) {
@@ -475,16 +502,12 @@ fc_status build_backward_tables(fc_batch* b) {
     voff += 3LL * b->meshes[m].n_verts;
     b->mesh_chunk0[m] = (int)chunks.size();
     b->mesh_vpart0[m] = vpart;
-    for (int g = 0; g < (int)b->grids.size(); ++g) {
-      std::vector<int> grp;
-      for (int oi = 0; oi < b->n_env; ++oi) {
-        const int e = b->order[oi];
-        if (b->env_mesh[e] == m && b->env_grid[e] == g) grp.push_back(e);
-      }
-      for (size_t i = 0; i < grp.size(); i += kBwdChunk) {
+    for (int g = 0; g < ng; ++g) {
+      const std::vector<int>& grp = groups[(size_t)m * ng + g];
+      for (size_t i = 0; i < grp.size(); i += chunk) {
         BwdChunk c;
         c.first = (int)env_list.size();
-        c.len = (int)std::min<size_t>(kBwdChunk, grp.size() - i);
+        c.len = (int)std::min<size_t>(chunk, grp.size() - i);
         c.n_tiles = b->mesh_tiles[m];
         c.mesh = m;
         c.vpart = vpart;

@@ -9,12 +9,16 @@
 
 namespace fcimpl {
 
-// Backward work decomposition.  These fix the order of every floating-point
-// sum in the adjoint, so they are constants, never tuned: the gradients are
-// bit-identical for every launch shape of the forward kernels.
-constexpr int kBwdTile = 512;   // vertices per backward item (pose partial sums)
-constexpr int kBwdBlock = 256;  // threads per backward workgroup (2 vertices each)
-constexpr int kBwdChunk = 32;   // environments per backward item (vertex partial sums)
+// Backward work decomposition.  Tile and block fix the order of every
+// per-env sum of the adjoint, so they are constants, never tuned.  The chunk
+// (envs per item, which orders the shared vertex sums) is chosen once per
+// batch at creation from the batch's shape and the device's resident
+// capacity (choose_bwd_chunk): the gradients are bit-identical for every
+// launch shape and call of a batch.
+constexpr int kBwdTile = 512;     // vertices per backward item (pose partial sums)
+constexpr int kBwdBlock = 256;    // threads per backward workgroup (2 vertices each)
+constexpr int kBwdChunkMin = 4;   // environments per backward item, at least ...
+constexpr int kBwdChunkMax = 64;  // ... and at most
 
 // Dispatch places workgroup i on XCD i mod kXcds (MI355X: 8 XCDs, one L2 each).
 constexpr int kXcds = 8;
@@ -119,7 +123,7 @@ struct BwdItem {
 
 struct BwdChunk {
   int first;      // into env_list
-  int len;        // envs in this chunk (<= kBwdChunk)
+  int len;        // envs in this chunk (<= kBwdChunkMax)
   int n_tiles;    // tiles of the chunk's mesh
   int mesh;
   long long vpart;  // offset (in float2) of this chunk's vertex partials [3][n_v]
@@ -185,5 +189,8 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int elem, int layout, int nx, int ny, int nz, int bx, int by,
                             int bz, hipStream_t s);
 bool forward_shape_supported(int block, int vpt);
+// workgroups of k_backward and of k_query_backward (the lower) that can be
+// resident on one compute unit at once, for a grid of dtype and layout
+int backward_blocks_per_cu(int dtype, int layout);
 
 }  // namespace fcimpl

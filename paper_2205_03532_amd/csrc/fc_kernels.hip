@@ -246,19 +246,26 @@ __device__ __forceinline__ int argmax_bin_lut(const BinCell* __restrict__ lut, c
                                               const float* __restrict__ dirs, int K, float nx, float ny,
                                               float nz) {
   if ((nx == 0.f) & (ny == 0.f) & (nz == 0.f)) return 0;
-  const BinCell c = lut[cube_cell(nx, ny, nz)];
-  const int n = c.n;
+  // the cell's 16 bytes (n, k[0..14]) in four registers; the loop is unrolled
+  // so every byte index is a constant (no private-array indexing)
+  const uint4 cw = *reinterpret_cast<const uint4*>(&lut[cube_cell(nx, ny, nz)]);
+  const unsigned w[4] = {cw.x, cw.y, cw.z, cw.w};
+  const int n = (int)(w[0] & 0xffu);
   if (n == kLutFull) return argmax_bin(dirs, K, nx, ny, nz);
-  int bin = c.k[0];
+  int bin = (int)((w[0] >> 8) & 0xffu);
   float4 d = dir4[bin];
   float best = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
-  for (int i = 1; i < n; ++i) {
-    const int k = c.k[i];
-    d = dir4[k];
-    const float v = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
-    if (v > best) {
-      best = v;
-      bin = k;
+#pragma unroll
+  for (int i = 1; i < kLutMax; ++i) {
+    if (i < n) {
+      const int b = i + 1;  // byte of k[i]
+      const int k = (int)((w[b >> 2] >> ((b & 3) * 8)) & 0xffu);
+      d = dir4[k];
+      const float v = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
+      if (v > best) {
+        best = v;
+        bin = k;
+      }
     }
   }
   return bin;
@@ -670,12 +677,14 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     vy[j] = ok[j] ? m.y[v] : 0.f;
     vz[j] = ok[j] ? m.z[v] : 0.f;
   }
-  float2 accv[V][3];
+  // the vertex-gradient sums of this thread's vertices, (sum, compensation)
+  // per component, kept in LDS (they change only for penetrating queries)
+  __shared__ float2 s_accv[V][3][kBwdBlock];
 #pragma unroll
-  for (int j = 0; j < V; ++j) accv[j][0] = accv[j][1] = accv[j][2] = make_float2(0.f, 0.f);
+  for (int j = 0; j < V; ++j) s_accv[j][0][tid] = s_accv[j][1][tid] = s_accv[j][2][tid] = make_float2(0.f, 0.f);
 
   // R, t and the upstream weight of the chunk's envs, computed once per item
-  __shared__ float4 s_pose[kBwdChunk][4];
+  __shared__ float4 s_pose[kBwdChunkMax][4];
   if (tid < ch.len) {
     const int e = A.env_list[ch.first + tid];
     const Rigid P = load_pose(A.pose, A.n_env, e);
@@ -686,23 +695,39 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
   }
   __syncthreads();
 
-  for (int c = 0; c < ch.len; ++c) {
-    const int e = A.env_list[ch.first + c];
-    const float4 p0 = s_pose[c][0], p1 = s_pose[c][1], p2 = s_pose[c][2];
-    const Rigid P{p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, p0.w, p1.w, p2.w};
-    const float up = s_pose[c][3].x;
-    float T[V][7];  // this lane's terms of the env's sums (zero where inactive)
-    bool any = false;
-    float xb[V], yb[V], zb[V];
+  // The env loop is software-pipelined over two register sets: the corner
+  // loads of env c + 1 are in flight while env c is evaluated.
+  struct Stage {
     Cell cl[V];
     float cc[V][8];
+  };
+  const auto pose_of = [&](int c) {
+    const float4 p0 = s_pose[c][0], p1 = s_pose[c][1], p2 = s_pose[c][2];
+    return Rigid{p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, p0.w, p1.w, p2.w};
+  };
+  const auto issue = [&](Stage& S, int c) {  // transform, locate, start the gather
+    const Rigid P = pose_of(c);
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      transform(P, vx[j], vy[j], vz[j], xb[j], yb[j], zb[j]);
-      cl[j] = locate(g, xb[j], yb[j], zb[j]);
+      float x, y, z;
+      transform(P, vx[j], vy[j], vz[j], x, y, z);
+      S.cl[j] = locate(g, x, y, z);
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) gather<DT, LAYOUT>(g, cl[j], cc[j]);
+    for (int j = 0; j < V; ++j) gather<DT, LAYOUT>(g, S.cl[j], S.cc[j]);
+  };
+  const auto finish = [&](Stage& S, int c) {  // everything after the gather
+    const int e = A.env_list[ch.first + c];
+    const Rigid P = pose_of(c);
+    const float up = s_pose[c][3].x;
+    const Cell* cl = S.cl;
+    const auto& cc = S.cc;
+    // x_B again (same arithmetic, same bits) rather than held across the pipeline
+    float xb[V], yb[V], zb[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) transform(P, vx[j], vy[j], vz[j], xb[j], yb[j], zb[j]);
+    float T[V][7];  // this lane's terms of the env's sums (zero where inactive)
+    bool any = false;
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       float phi, gx, gy, gz;
@@ -739,9 +764,13 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
         dvy = up * fmaf(P.r01, wx, fmaf(P.r11, wy, P.r21 * wz));
         dvz = up * fmaf(P.r02, wx, fmaf(P.r12, wy, P.r22 * wz));
         if (shared_v) {
-          nadd(accv[j][0], dvx);
-          nadd(accv[j][1], dvy);
-          nadd(accv[j][2], dvz);
+          float2 a0 = s_accv[j][0][tid], a1 = s_accv[j][1][tid], a2 = s_accv[j][2][tid];
+          nadd(a0, dvx);
+          nadd(a1, dvy);
+          nadd(a2, dvz);
+          s_accv[j][0][tid] = a0;
+          s_accv[j][1][tid] = a1;
+          s_accv[j][2][tid] = a2;
         }
       }
       if (A.per_env && A.d_verts && ok[j]) {
@@ -778,6 +807,14 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     }
     if (lane < 8)
       A.pose_part[((long long)(A.env_tile_base[e] + it.tile_in_mesh) * NW + wave) * 8 + wave_sum8_slot(lane)] = red;
+  };
+  Stage SA, SB;
+  if (ch.len > 0) issue(SA, 0);
+  for (int c = 0; c < ch.len; c += 2) {
+    if (c + 1 < ch.len) issue(SB, c + 1);
+    finish(SA, c);
+    if (c + 2 < ch.len) issue(SA, c + 2);
+    if (c + 1 < ch.len) finish(SB, c + 1);
   }
 
   if (shared_v) {
@@ -787,9 +824,9 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     for (int j = 0; j < V; ++j) {
       if (!ok[j]) continue;
       const int v = it.vstart + j * kBwdBlock + tid;
-      A.vert_part[base + v] = accv[j][0];
-      A.vert_part[base + n + v] = accv[j][1];
-      A.vert_part[base + 2 * (long long)n + v] = accv[j][2];
+      A.vert_part[base + v] = s_accv[j][0][tid];
+      A.vert_part[base + n + v] = s_accv[j][1][tid];
+      A.vert_part[base + 2 * (long long)n + v] = s_accv[j][2][tid];
     }
   }
 }
@@ -1039,6 +1076,31 @@ hipError_t bwd_dtype(const BwdArgs& a, int dtype, int layout, hipStream_t s) {
 }
 
 }  // namespace
+
+template <int DT, int LAYOUT>
+int bwd_occupancy() {
+  int a = 0, b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_backward<DT, LAYOUT>, kBwdBlock, 0) != hipSuccess) a = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_query_backward<DT, LAYOUT>, kBwdBlock, 0) != hipSuccess)
+    b = 1;
+  return std::max(1, std::min(a, b));
+}
+
+template <int DT>
+int bwd_occupancy_layout(int layout) {
+  if (layout == FC_LAYOUT_BRICK) return bwd_occupancy<DT, FC_LAYOUT_BRICK>();
+  if (layout == FC_LAYOUT_SLAB) return bwd_occupancy<DT, FC_LAYOUT_SLAB>();
+  return bwd_occupancy<DT, FC_LAYOUT_LINEAR>();
+}
+
+int backward_blocks_per_cu(int dtype, int layout) {
+  switch (dtype) {
+    case kF32: return bwd_occupancy_layout<kF32>(layout);
+    case kF16: return bwd_occupancy_layout<kF16>(layout);
+    case kBF16: return bwd_occupancy_layout<kBF16>(layout);
+  }
+  return 1;
+}
 
 bool forward_shape_supported(int block, int vpt) {
   return (block == 128 || block == 256 || block == 512) && (vpt == 1 || vpt == 2 || vpt == 4);
