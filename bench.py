@@ -252,6 +252,17 @@ def main():
     k_one, kid = batch.read_timing()
     assert len(k_one) == n and np.all(kid == fc.FC_KERNEL_QUERY_BACKWARD)
 
+    # the achievable gather rate of this path: the same kernel loop and loads with no
+    # arithmetic (fc_gather_probe), timed the same way
+    sink = torch.zeros(1, device=dev)
+    for _ in range(args.warmup):
+        fc.fc_gather_probe(batch, pose, sink)
+    batch.set_timing(n)
+    for _ in range(n):
+        fc.fc_gather_probe(batch, pose, sink)
+    k_probe, kid = batch.read_timing()
+    assert len(k_probe) == n and np.all(kid == fc.FC_KERNEL_GATHER_PROBE)
+
     # the separate forms, for comparison (not part of the step)
     out2 = batch.new_contacts()
     grads2 = batch.new_grads(per_env=False)
@@ -334,6 +345,12 @@ def main():
             "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "alg_bytes_per_query": bpq,
+            "achievable_gather": {
+                "probe": "fc_gather_probe: the same kernel loop, work items and corner loads, no arithmetic",
+                "probe_ms": float(k_probe.mean()),
+                "probe_GBps": bpq * Q / (float(k_probe.mean()) * 1e-3) / 1e9,
+                "frac": float(k_probe.mean()) / kms,
+            },
         },
     }
     if not args.no_cpu_baseline:

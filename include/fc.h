@@ -303,7 +303,8 @@ int32_t fc_batch_signature(const fc_batch* batch, char* buf, int32_t cap);
 typedef enum fc_kernel_id {
   FC_KERNEL_FORWARD = 0,        /* k_forward (any mode) */
   FC_KERNEL_BACKWARD = 1,       /* k_backward */
-  FC_KERNEL_QUERY_BACKWARD = 2  /* k_query_backward */
+  FC_KERNEL_QUERY_BACKWARD = 2, /* k_query_backward */
+  FC_KERNEL_GATHER_PROBE = 3    /* k_gather_probe */
 } fc_kernel_id;
 fc_status fc_batch_set_timing(fc_batch* batch, int32_t max_records);
 /* Waits for the recorded launches and writes, for the first min(recorded,
@@ -312,6 +313,17 @@ fc_status fc_batch_set_timing(fc_batch* batch, int32_t max_records);
  * Returns the number written, or -1 (NULL arguments, or a HIP error: see
  * fc_last_hip_error). */
 int32_t fc_batch_read_timing(fc_batch* batch, float* ms, int32_t* kernel, int32_t max);
+
+/* Measurement aid: the achievable gather rate of the one-pass path.  Runs
+ * fc_sdf_query_and_backward's kernel loop -- the same work items, env
+ * pipelining, vertex and pose reads and 8-corner loads per query, at the same
+ * addresses -- with no arithmetic beyond summing each query's corners.  The
+ * sums are discarded: sink (device, one float) is written only if a sum
+ * equals -1.5e38, which the probe's inputs never produce.  Time it with
+ * fc_batch_set_timing (kernel id FC_KERNEL_GATHER_PROBE); the ratio of its
+ * duration to k_query_backward's is the fraction of the achievable gather
+ * rate the full path reaches.  Writes nothing else; needs no workspace. */
+fc_status fc_gather_probe(const fc_batch* batch, const float* pose, float* sink, void* stream);
 
 const char* fc_status_str(fc_status status);
 int32_t fc_last_hip_error(void); /* hipError_t of the last FC_ERR_HIP on this thread */

@@ -665,9 +665,11 @@ BwdArgs make_bwd(const fc_batch* b, const float* pose, float k, const float* ups
   a.loss = out->loss;
   a.d_pose = out->d_pose;
   a.d_verts = out->d_verts;
-  char* w = static_cast<char*>(ws);
-  a.pose_part = reinterpret_cast<float2*>(w + b->off_pose);
-  a.vert_part = reinterpret_cast<float2*>(w + b->off_vert);
+  if (ws) {
+    char* w = static_cast<char*>(ws);
+    a.pose_part = reinterpret_cast<float2*>(w + b->off_pose);
+    a.vert_part = reinterpret_cast<float2*>(w + b->off_vert);
+  }
   return a;
 }
 
@@ -893,6 +895,18 @@ fc_status fc_sdf_query_and_backward(const fc_batch* b, const float* pose, const 
   fc_status s = validate_backward(b, pose, k, grads, ws, ws_bytes);
   if (s != FC_OK) return s;
   return enqueue_query_backward(b, pose, fused_out, k, upstream, grads, ws, (hipStream_t)stream, true);
+}
+
+fc_status fc_gather_probe(const fc_batch* b, const float* pose, float* sink, void* stream) {
+  if (!b || !pose || !sink) return FC_ERR_NULL;
+  fc_grads g;
+  std::memset(&g, 0, sizeof(g));
+  g.loss = sink;  // the probe's only store target (taken only by a sentinel sum)
+  BwdArgs a = make_bwd(b, pose, 1.f, nullptr, &g, nullptr);
+  KernelMarks m;
+  FC_HIP(launch_gather_probe(a, b->dtype, b->layout, (hipStream_t)stream,
+                             take_marks(b, FC_KERNEL_GATHER_PROBE, true, m)));
+  return FC_OK;
 }
 
 struct fc_graph {

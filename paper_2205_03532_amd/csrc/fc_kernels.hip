@@ -640,6 +640,10 @@ __device__ __forceinline__ float2 wave_sum8(const float2 a[8]) {
 }
 
 struct NoQuery {};
+// Measurement mode: the same items, loop and loads, and no arithmetic beyond
+// summing the corners (kept live by a store that a sentinel sum would take).
+struct GatherOnly {};
+constexpr float kProbeSentinel = -1.5e38f;
 
 // One backward work item: a tile of kBwdTile vertices of one mesh against the
 // envs of one chunk.  With QX = QueryExtra the same pass also forms the
@@ -649,7 +653,8 @@ struct NoQuery {};
 template <int DT, int LAYOUT, class QX>
 __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, unsigned long long* s_wkeys,
                                               const BinCell* s_lut, const float4* s_dir4) {
-  constexpr bool QUERY = !__is_same(QX, NoQuery);
+  constexpr bool PROBE = __is_same(QX, GatherOnly);
+  constexpr bool QUERY = !__is_same(QX, NoQuery) && !PROBE;
   constexpr int V = kBwdTile / kBwdBlock;
   static_assert(V >= 2, "lane pairs start from two terms");
   constexpr int NW = kBwdBlock / 64;
@@ -717,6 +722,15 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     for (int j = 0; j < V; ++j) gather<DT, LAYOUT>(g, S.cl[j], S.cc[j]);
   };
   const auto finish = [&](Stage& S, int c) {  // everything after the gather
+    if constexpr (PROBE) {
+      float sum = 0.f;
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sum += S.cc[j][q];
+      if (sum == kProbeSentinel) A.loss[0] = sum;
+      return;
+    }
     const int e = A.env_list[ch.first + c];
     const Rigid P = pose_of(c);
     const float up = s_pose[c][3].x;
@@ -817,7 +831,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     if (c + 1 < ch.len) finish(SB, c + 1);
   }
 
-  if (shared_v) {
+  if (!PROBE && shared_v) {
     const long long base = A.chunks[it.chunk].vpart;
     const int n = m.n;
 #pragma unroll
@@ -834,6 +848,11 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
 template <int DT, int LAYOUT>
 __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
   backward_item<DT, LAYOUT>(A, NoQuery{}, nullptr, nullptr, nullptr);
+}
+
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(kBwdBlock) void k_gather_probe(BwdArgs A) {
+  backward_item<DT, LAYOUT>(A, GatherOnly{}, nullptr, nullptr, nullptr);
 }
 
 // Query and adjoint in one pass: the bin-search tables go to LDS as in
@@ -1052,6 +1071,23 @@ hipError_t qbwd_launch(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, 
   return combine_launch(a, s);
 }
 
+template <int DT, int LAYOUT>
+hipError_t probe_launch(const BwdArgs& a, hipStream_t s) {
+  hipError_t e = mark(false, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gather_probe<DT, LAYOUT>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return mark(true, s);
+}
+
+template <int DT>
+hipError_t probe_layout(const BwdArgs& a, int layout, hipStream_t s) {
+  if (layout == FC_LAYOUT_BRICK) return probe_launch<DT, FC_LAYOUT_BRICK>(a, s);
+  if (layout == FC_LAYOUT_SLAB) return probe_launch<DT, FC_LAYOUT_SLAB>(a, s);
+  return probe_launch<DT, FC_LAYOUT_LINEAR>(a, s);
+}
+
 template <int DT>
 hipError_t qbwd_layout(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, int layout, hipStream_t s) {
   if (layout == FC_LAYOUT_BRICK) return qbwd_launch<DT, FC_LAYOUT_BRICK>(a, q, f, s);
@@ -1134,6 +1170,17 @@ hipError_t launch_query_backward(const BwdArgs& a, const QueryExtra& q, const Fw
     case kF32: return qbwd_layout<kF32>(a, q, payload, layout, s);
     case kF16: return qbwd_layout<kF16>(a, q, payload, layout, s);
     case kBF16: return qbwd_layout<kBF16>(a, q, payload, layout, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gather_probe(const BwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m) {
+  if (a.n_items <= 0) return hipSuccess;
+  const MarksScope scope(m);
+  switch (dtype) {
+    case kF32: return probe_layout<kF32>(a, layout, s);
+    case kF16: return probe_layout<kF16>(a, layout, s);
+    case kBF16: return probe_layout<kBF16>(a, layout, s);
   }
   return hipErrorInvalidValue;
 }

@@ -17,7 +17,7 @@ import os
 
 import numpy as np
 
-FC_KERNEL_FORWARD, FC_KERNEL_BACKWARD, FC_KERNEL_QUERY_BACKWARD = 0, 1, 2
+FC_KERNEL_FORWARD, FC_KERNEL_BACKWARD, FC_KERNEL_QUERY_BACKWARD, FC_KERNEL_GATHER_PROBE = 0, 1, 2, 3
 
 # the in-tree build; FC_LIB_PATH selects another build of the same sources
 LIB_PATH = os.environ.get("FC_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -93,6 +93,7 @@ SIGNATURES = {
     "fc_batch_signature": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32]),
     "fc_batch_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "fc_batch_read_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32]),
+    "fc_gather_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fc_status_str": (C.c_char_p, [C.c_int]),
     "fc_last_hip_error": (C.c_int32, []),
     "fc_version": (C.c_char_p, []),
@@ -330,6 +331,11 @@ def fc_sdf_query_and_backward(batch: Batch, pose, fused_out, k, grads, upstream=
                                            _ptr(upstream), C.byref(_grads_struct(grads)),
                                            C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes,
                                            _stream(stream)), "fc_sdf_query_and_backward")
+
+
+def fc_gather_probe(batch: Batch, pose, sink, stream=None):
+    """The one-pass kernel's loads without its arithmetic (a measurement aid)."""
+    _check(lib().fc_gather_probe(batch.handle, _ptr(pose), _ptr(sink), _stream(stream)), "fc_gather_probe")
 
 
 class Graph:

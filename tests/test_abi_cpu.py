@@ -103,6 +103,7 @@ def test_null_arguments(L):
     assert L.fc_sdf_query_backward(None, None, 1.0, None, None, None, 0, None) == fc.FC_ERR_NULL
     assert L.fc_sdf_query_and_backward(None, None, None, 1.0, None, None, None, 0, None) == fc.FC_ERR_NULL
     assert L.fc_graph_launch(None, None) == fc.FC_ERR_NULL
+    assert L.fc_gather_probe(None, None, None, None) == fc.FC_ERR_NULL
     assert L.fc_batch_set_timing(None, 4) == fc.FC_ERR_NULL
     assert L.fc_batch_read_timing(None, None, None, 0) == -1
     assert L.fc_batch_queries(None) == -1

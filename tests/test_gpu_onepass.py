@@ -175,3 +175,22 @@ def test_kernel_timing_records_main_kernels_only():
     b.set_timing(0)
     fc.fc_sdf_query(b, pose, fused_out=o)
     assert len(b.read_timing()[0]) == 0
+
+
+def test_gather_probe_writes_nothing_and_is_timed():
+    """The gather probe (the one-pass loop without its arithmetic) leaves its
+    sink and every output untouched and is recorded under its own kernel id."""
+    torch = torch_gpu()
+    w = W.subset(W.nut_bolt_workload(), range(24))
+    b = fc.Batch.from_workload(w, layout="brick")
+    pose = fc.pose_tensor(w.pose)
+    sink = torch.full((4,), 7.0, device="cuda")
+    ws_before = b.workspace.clone()
+    b.set_timing(2)
+    fc.fc_gather_probe(b, pose, sink)
+    fc.fc_gather_probe(b, pose, sink)
+    ms, kid = b.read_timing()
+    b.set_timing(0)
+    assert list(kid) == [fc.FC_KERNEL_GATHER_PROBE] * 2 and np.all(ms > 0)
+    assert torch.equal(sink, torch.full((4,), 7.0, device="cuda"))
+    assert torch.equal(b.workspace, ws_before)
