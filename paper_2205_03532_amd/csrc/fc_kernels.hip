@@ -572,9 +572,13 @@ __device__ __forceinline__ void nadd(float2& a, float x) {
   a.y += (fabsf(a.x) >= fabsf(x)) ? ((a.x - t) + x) : ((x - t) + a.x);
   a.x = t;
 }
+// Sum of two (sum, compensation) pairs: the sums' exact rounding error (by
+// branch-free TwoSum, the same value as the ordered Fast2Sum of Neumaier's
+// step) joins the compensations.
 __device__ __forceinline__ float2 ncombine(float2 a, float2 b) {
   const float t = a.x + b.x;
-  const float e = (fabsf(a.x) >= fabsf(b.x)) ? ((a.x - t) + b.x) : ((b.x - t) + a.x);
+  const float bb = t - a.x;
+  const float e = (a.x - (t - bb)) + (b.x - bb);
   return make_float2(t, (a.y + b.y) + e);
 }
 
@@ -700,8 +704,9 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
   }
   __syncthreads();
 
-  // The env loop is software-pipelined over two register sets: the corner
-  // loads of env c + 1 are in flight while env c is evaluated.
+  // With two vertices per thread the env loop is software-pipelined over two
+  // register sets: the corner loads of env c + 1 are in flight while env c is
+  // evaluated.
   struct Stage {
     Cell cl[V];
     float cc[V][8];
@@ -822,13 +827,21 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     if (lane < 8)
       A.pose_part[((long long)(A.env_tile_base[e] + it.tile_in_mesh) * NW + wave) * 8 + wave_sum8_slot(lane)] = red;
   };
-  Stage SA, SB;
-  if (ch.len > 0) issue(SA, 0);
-  for (int c = 0; c < ch.len; c += 2) {
-    if (c + 1 < ch.len) issue(SB, c + 1);
-    finish(SA, c);
-    if (c + 2 < ch.len) issue(SA, c + 2);
-    if (c + 1 < ch.len) finish(SB, c + 1);
+  if constexpr (V <= 2) {
+    Stage SA, SB;
+    if (ch.len > 0) issue(SA, 0);
+    for (int c = 0; c < ch.len; c += 2) {
+      if (c + 1 < ch.len) issue(SB, c + 1);
+      finish(SA, c);
+      if (c + 2 < ch.len) issue(SA, c + 2);
+      if (c + 1 < ch.len) finish(SB, c + 1);
+    }
+  } else {  // enough loads per env in flight without a second register set
+    Stage S;
+    for (int c = 0; c < ch.len; ++c) {
+      issue(S, c);
+      finish(S, c);
+    }
   }
 
   if (!PROBE && shared_v) {

@@ -59,3 +59,31 @@ def test_nut_bolt_locality_order_follows_the_axis():
     z = w.pose[6, o]
     # lateral jitter is tiny next to the axial range: the order is nearly sorted in z
     assert np.mean(np.diff(z) >= -1e-4) > 0.9
+
+
+def test_twosum_equals_ordered_fast2sum_in_float32():
+    """The adjoint's pair combine takes the rounding error of a + b by
+    branch-free TwoSum; in float32 it equals the magnitude-ordered Fast2Sum of
+    Neumaier's step bit for bit (both are the exact error), so the switch does
+    not change a single sum."""
+    rng = np.random.default_rng(5)
+    f = np.float32
+    a = (rng.standard_normal(200000) * np.exp(rng.uniform(-30, 30, 200000))).astype(f)
+    b = (rng.standard_normal(200000) * np.exp(rng.uniform(-30, 30, 200000))).astype(f)
+    b[:1000] = -a[:1000]  # exact cancellation
+    b[1000:2000] = a[1000:2000]
+    with np.errstate(over="ignore", invalid="ignore"):
+        t = a + b
+        bb = t - a
+        two = (a - (t - bb)) + (b - bb)
+        ordered = np.where(np.abs(a) >= np.abs(b), (a - t) + b, (b - t) + a)
+    ok = np.isfinite(t)
+    assert np.array_equal(two[ok], ordered[ok])
+    # and it is the exact error (checked where float64 holds a + b exactly:
+    # exponents less than 29 binades apart)
+    with np.errstate(divide="ignore"):
+        close = np.abs(np.log2(np.abs(a.astype(np.float64))) - np.log2(np.abs(b.astype(np.float64)))) < 28
+    exact = (a.astype(np.float64) + b.astype(np.float64)) - t.astype(np.float64)
+    sel = ok & close
+    assert sel.sum() > 10000
+    assert np.array_equal(two[sel].astype(np.float64), exact[sel])
