@@ -170,6 +170,10 @@ typedef struct fc_grads {
  *   persistent  0: one workgroup per item; 1: a grid of about
  *               grid_mult workgroups per compute unit pulling items in a
  *               fixed order; 2: the same pulling items from an atomic counter;
+ *               3: the fused forward (fc_sdf_query with fused_out and no
+ *               cand) on the adjoint's work items -- a vertex tile against a
+ *               chunk of envs, one resident round, env loads pipelined; block,
+ *               tile and grid_mult then do not apply;
  *   grid_mult   workgroups per compute unit for persistent launches (1..32);
  *   xcd_remap   1: split the items into 8 contiguous ranges, one per XCD
  *               (each XCD has its own L2), for the forward and the adjoint. */

@@ -1,8 +1,9 @@
 """Launch-shape autotuner for the forward kernels.
 
 For one batch it times every valid launch shape (threads per workgroup,
-vertices per work item, plain / persistent-static / persistent-dynamic
-scheduling, workgroups per compute unit) with HIP events on the current
+vertices per work item, plain / persistent-static / persistent-dynamic /
+env-chunked scheduling, workgroups per compute unit, XCD ranges) with HIP
+events on the current
 stream, checks that each shape's contacts are bit-identical to the default
 shape's (the reduction is an integer max, so any difference is a bug), and
 records the fastest in a JSON cache keyed by the batch signature:
@@ -38,6 +39,9 @@ def candidate_shapes():
                     for xr in (0, 1):
                         out.append(dict(block=block, tile=block * vpt, persistent=persistent, grid_mult=gm,
                                         xcd_remap=xr))
+    # env-chunked items (block, tile and grid_mult do not apply)
+    for xr in (0, 1):
+        out.append(dict(DEFAULT, persistent=3, xcd_remap=xr))
     return out
 
 

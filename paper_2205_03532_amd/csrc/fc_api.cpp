@@ -114,7 +114,7 @@ fc_status validate_desc(const fc_batch_desc* d) {
 bool launch_valid(const fc_launch& l) {
   if (l.block <= 0 || l.tile <= 0 || l.tile % l.block) return false;
   if (!forward_shape_supported(l.block, l.tile / l.block)) return false;
-  if (l.persistent < 0 || l.persistent > 2) return false;
+  if (l.persistent < 0 || l.persistent > 3) return false;
   if (l.grid_mult < 1 || l.grid_mult > 32) return false;
   if (l.xcd_remap < 0 || l.xcd_remap > 1) return false;
   return true;
@@ -610,8 +610,14 @@ FwdArgs make_fwd(const fc_batch* b, const float* pose, const fc_candidates* cand
   return a;
 }
 
+// The per-item forward kernel's scheduling mode: the env-chunked mode (3)
+// applies to the fused-only call, any other call runs per item as a plain
+// launch.
+int item_persistent(const fc_batch* b) { return b->launch.persistent == 3 ? 0 : b->launch.persistent; }
+
 int forward_grid(const fc_batch* b) {
-  const fc_launch& l = b->launch;
+  fc_launch l = b->launch;
+  l.persistent = item_persistent(b);
   if (!l.xcd_remap) {
     if (l.persistent == 0) return b->n_items;
     return (int)std::min<long long>((long long)b->num_cus * l.grid_mult, b->n_items);
@@ -627,12 +633,35 @@ bool contacts_ok(const fc_contacts* o) {
   return o->vidx && o->depth && o->point && o->normal && o->count;
 }
 
+BwdArgs make_bwd(const fc_batch* b, const float* pose, float k, const float* upstream, const fc_grads* out, void* ws);
+
+QueryExtra make_query_extra(const fc_batch* b, const FwdArgs& f) {
+  QueryExtra q;
+  std::memset(&q, 0, sizeof(q));
+  for (int i = 0; i < 3 * b->K; ++i) q.dirs[i] = b->dirs[i];
+  q.bin_lut = b->d_lut;
+  q.K = b->K;
+  q.margin = b->margin;
+  q.keys = f.keys;
+  return q;
+}
+
 fc_status enqueue_forward(const fc_batch* b, const float* pose, const fc_candidates* cand, const fc_contacts* out,
                           void* ws, hipStream_t s, bool from_cand, bool timed) {
   const FwdArgs a = make_fwd(b, pose, cand, out, ws);
+  if (b->launch.persistent == 3 && out && !cand && !from_cand) {
+    // fused query + reduction on the adjoint's env-chunked items
+    fc_grads none;
+    std::memset(&none, 0, sizeof(none));
+    const BwdArgs ba = make_bwd(b, pose, 1.f, nullptr, &none, nullptr);
+    KernelMarks m;
+    FC_HIP(launch_query_chunked(ba, make_query_extra(b, a), a, b->dtype, b->layout, s,
+                                take_marks(b, FC_KERNEL_FORWARD, timed, m)));
+    return FC_OK;
+  }
   const int vpt = b->launch.tile / b->launch.block;
   KernelMarks m;
-  FC_HIP(launch_forward(a, b->dtype, b->layout, b->launch.block, vpt, b->launch.persistent, b->launch.xcd_remap,
+  FC_HIP(launch_forward(a, b->dtype, b->layout, b->launch.block, vpt, item_persistent(b), b->launch.xcd_remap,
                         forward_grid(b), from_cand, s, take_marks(b, FC_KERNEL_FORWARD, timed, m)));
   return FC_OK;
 }
@@ -686,13 +715,7 @@ fc_status enqueue_query_backward(const fc_batch* b, const float* pose, const fc_
                                  const float* upstream, const fc_grads* out, void* ws, hipStream_t s, bool timed) {
   const BwdArgs a = make_bwd(b, pose, k, upstream, out, ws);
   const FwdArgs f = make_fwd(b, pose, nullptr, contacts, ws);
-  QueryExtra q;
-  std::memset(&q, 0, sizeof(q));
-  for (int i = 0; i < 3 * b->K; ++i) q.dirs[i] = b->dirs[i];
-  q.bin_lut = b->d_lut;
-  q.K = b->K;
-  q.margin = b->margin;
-  q.keys = f.keys;
+  const QueryExtra q = make_query_extra(b, f);
   KernelMarks m;
   FC_HIP(launch_query_backward(a, q, f, b->dtype, b->layout, s, take_marks(b, FC_KERNEL_QUERY_BACKWARD, timed, m)));
   return FC_OK;

@@ -185,6 +185,10 @@ hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t 
 // outputs and keys) and the adjoint's combine
 hipError_t launch_query_backward(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,
                                  hipStream_t s, const KernelMarks* m);
+// the fused forward on the adjoint's env-chunked work items (fc_launch
+// persistent = 3): k_query_chunked, then the payload
+hipError_t launch_query_chunked(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,
+                                hipStream_t s, const KernelMarks* m);
 // measurement aid: k_query_backward's items, loop and corner loads, no arithmetic
 hipError_t launch_gather_probe(const BwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -547,9 +547,9 @@ __global__ __launch_bounds__(BLOCK) void k_forward(FwdArgs A, int persistent, in
 // (resetting it to zero for the next call), writes the slot and the count,
 // and resets the persistent work counters.
 template <int DT, int LAYOUT>
-__global__ __launch_bounds__(256) void k_payload(FwdArgs A, int from_cand) {
-  if (blockIdx.x == 0 && threadIdx.x < kXcds) A.work_ctr[threadIdx.x] = 0u;
-  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void payload_block(const FwdArgs& A, int from_cand, int block) {
+  if (block == 0 && threadIdx.x < kXcds) A.work_ctr[threadIdx.x] = 0u;
+  const int e = block * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (e >= A.n_env) return;
   unsigned long long key = 0ull;
@@ -561,6 +561,11 @@ __global__ __launch_bounds__(256) void k_payload(FwdArgs A, int from_cand) {
   }
   const unsigned long long nonempty = __ballot((lane < A.K) && (key != 0ull));
   if (lane == 0) A.o_count[e] = __popcll(nonempty);
+}
+
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(256) void k_payload(FwdArgs A, int from_cand) {
+  payload_block<DT, LAYOUT>(A, from_cand, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,11 +659,11 @@ constexpr float kProbeSentinel = -1.5e38f;
 // forward's candidates and per-bin maxima (one gather serves both): each
 // wavefront keeps its own K keys in LDS, flushed to the env's global keys
 // after every env.
-template <int DT, int LAYOUT, class QX>
+template <int DT, int LAYOUT, class QX, bool ADJ = true>
 __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, unsigned long long* s_wkeys,
                                               const BinCell* s_lut, const float4* s_dir4) {
   constexpr bool PROBE = __is_same(QX, GatherOnly);
-  constexpr bool QUERY = !__is_same(QX, NoQuery) && !PROBE;
+  constexpr bool QUERY = !__is_same(QX, NoQuery) && !PROBE;  // ADJ = false: the query half alone
   constexpr int V = kBwdTile / kBwdBlock;
   static_assert(V >= 2, "lane pairs start from two terms");
   constexpr int NW = kBwdBlock / 64;
@@ -689,8 +694,10 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
   // the vertex-gradient sums of this thread's vertices, (sum, compensation)
   // per component, kept in LDS (they change only for penetrating queries)
   __shared__ float2 s_accv[V][3][kBwdBlock];
+  if constexpr (ADJ) {
 #pragma unroll
-  for (int j = 0; j < V; ++j) s_accv[j][0][tid] = s_accv[j][1][tid] = s_accv[j][2][tid] = make_float2(0.f, 0.f);
+    for (int j = 0; j < V; ++j) s_accv[j][0][tid] = s_accv[j][1][tid] = s_accv[j][2][tid] = make_float2(0.f, 0.f);
+  }
 
   // R, t and the upstream weight of the chunk's envs, computed once per item
   __shared__ float4 s_pose[kBwdChunkMax][4];
@@ -737,10 +744,31 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
       return;
     }
     const int e = A.env_list[ch.first + c];
-    const Rigid P = pose_of(c);
-    const float up = s_pose[c][3].x;
     const Cell* cl = S.cl;
     const auto& cc = S.cc;
+    if constexpr (!ADJ) {  // the forward's candidates, bins and per-bin maxima only
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        float phi, gx, gy, gz;
+        trilinear(cc[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
+        if (ok[j] & cl[j].inside & (phi < F.margin)) {
+          float nx, ny, nz;
+          normalize(gx, gy, gz, nx, ny, nz);
+          const int bin = argmax_bin_lut(s_lut, s_dir4, F.dirs, F.K, nx, ny, nz);
+          atomicMax(&s_wkeys[bin], make_key(-phi, (unsigned)(it.vstart + j * kBwdBlock + tid)));
+        }
+      }
+      if (lane < F.K) {
+        const unsigned long long kk = s_wkeys[lane];
+        if (kk) {
+          atomicMax(&F.keys[(long long)e * F.K + lane], kk);
+          s_wkeys[lane] = 0ull;
+        }
+      }
+      return;
+    }
+    const Rigid P = pose_of(c);
+    const float up = s_pose[c][3].x;
     // x_B again (same arithmetic, same bits) rather than held across the pipeline
     float xb[V], yb[V], zb[V];
 #pragma unroll
@@ -844,7 +872,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     }
   }
 
-  if (!PROBE && shared_v) {
+  if (ADJ && !PROBE && shared_v) {
     const long long base = A.chunks[it.chunk].vpart;
     const int n = m.n;
 #pragma unroll
@@ -868,10 +896,11 @@ __global__ __launch_bounds__(kBwdBlock) void k_gather_probe(BwdArgs A) {
   backward_item<DT, LAYOUT>(A, GatherOnly{}, nullptr, nullptr, nullptr);
 }
 
-// Query and adjoint in one pass: the bin-search tables go to LDS as in
-// k_forward, plus K keys per wavefront.
-template <int DT, int LAYOUT>
-__global__ __launch_bounds__(kBwdBlock) void k_query_backward(BwdArgs A, QueryExtra F) {
+// Query and adjoint in one pass (ADJ), or the query alone on the same work
+// items (the forward's env-chunked mode): the bin-search tables go to LDS as
+// in k_forward, plus K keys per wavefront.
+template <int DT, int LAYOUT, bool ADJ>
+__device__ __forceinline__ void query_chunked_body(const BwdArgs& A, const QueryExtra& F) {
   __shared__ BinCell s_lut[kLutCells];
   __shared__ float4 s_dir4[FC_MAX_BINS];
   __shared__ unsigned long long s_keys[kBwdBlock / 64][FC_MAX_BINS];
@@ -886,7 +915,17 @@ __global__ __launch_bounds__(kBwdBlock) void k_query_backward(BwdArgs A, QueryEx
   }
   s_keys[threadIdx.x >> 6][threadIdx.x & 63] = 0ull;
   __syncthreads();
-  backward_item<DT, LAYOUT>(A, F, s_keys[threadIdx.x >> 6], s_lut, s_dir4);
+  backward_item<DT, LAYOUT, QueryExtra, ADJ>(A, F, s_keys[threadIdx.x >> 6], s_lut, s_dir4);
+}
+
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(kBwdBlock) void k_query_backward(BwdArgs A, QueryExtra F) {
+  query_chunked_body<DT, LAYOUT, true>(A, F);
+}
+
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(kBwdBlock) void k_query_chunked(BwdArgs A, QueryExtra F) {
+  query_chunked_body<DT, LAYOUT, false>(A, F);
 }
 
 // Fixed-order combine of the adjoint's partial sums.  Workgroups
@@ -896,11 +935,11 @@ __global__ __launch_bounds__(kBwdBlock) void k_query_backward(BwdArgs A, QueryEx
 // thread and sum the chunks in order, loads issued eight at a time.
 constexpr int kCombineBatch = 8;
 
-__global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, long long n_vert_total,
-                                                     int pose_blocks) {
+__device__ __forceinline__ void combine_block(const BwdArgs& A, int shared_v, long long n_vert_total,
+                                             int pose_blocks, int block) {
   constexpr int NW = kBwdBlock / 64;
-  if ((int)blockIdx.x < pose_blocks) {
-    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (block < pose_blocks) {
+    const int e = block * 4 + (threadIdx.x >> 6);
     if (e >= A.n_env) return;  // whole wavefront leaves together
     const int lane = threadIdx.x & 63;
     const int n_rows = A.mesh_tiles[A.envs[e].gm >> 8] * NW;  // (tile, wave) rows in order
@@ -926,7 +965,7 @@ __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, lo
     return;
   }
   if (!shared_v) return;
-  const long long jj = (long long)(blockIdx.x - pose_blocks) * blockDim.x + threadIdx.x;
+  const long long jj = (long long)(block - pose_blocks) * blockDim.x + threadIdx.x;
   if (jj >= 3 * n_vert_total) return;
   const int comp = (int)(jj / n_vert_total);
   long long j = jj - (long long)comp * n_vert_total;
@@ -950,6 +989,23 @@ __global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, lo
       if (c0 + b < nc) r = (c0 + b == 0) ? buf[b] : ncombine(r, buf[b]);
   }
   A.d_verts[A.mesh_voff[m] + comp * n + j] = r.x + r.y;
+}
+
+__global__ __launch_bounds__(256) void k_bwd_combine(BwdArgs A, int shared_v, long long n_vert_total,
+                                                     int pose_blocks) {
+  combine_block(A, shared_v, n_vert_total, pose_blocks, blockIdx.x);
+}
+
+// The one pass's two tails in one launch: workgroups [0, payload_blocks)
+// write the contact slots, the rest combine the adjoint's partial sums (the
+// two read and write disjoint data).
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(256) void k_tail(FwdArgs F, BwdArgs A, int shared_v, long long n_vert_total,
+                                              int pose_blocks, int payload_blocks) {
+  if ((int)blockIdx.x < payload_blocks)
+    payload_block<DT, LAYOUT>(F, 0, blockIdx.x);
+  else
+    combine_block(A, shared_v, n_vert_total, pose_blocks, blockIdx.x - payload_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1046,14 +1102,25 @@ hipError_t fwd_layout(const FwdArgs& a, int layout, int block, int vpt, int pers
 
 int bwd_grid(const BwdArgs& a) { return a.xcd ? kXcds * ((a.n_items + kXcds - 1) / kXcds) : a.n_items; }
 
+struct CombineShape {
+  int shared_v, pose_blocks;
+  long long nv, vert_blocks;
+};
+
+CombineShape combine_shape(const BwdArgs& a) {
+  CombineShape c;
+  c.shared_v = (a.d_verts != nullptr) && !a.per_env;
+  c.nv = 0;
+  for (int m = 0; m < a.n_meshes; ++m) c.nv += a.meshes[m].n;
+  c.pose_blocks = (a.n_env + 3) / 4;
+  c.vert_blocks = c.shared_v ? (3 * c.nv + 255) / 256 : 0;
+  return c;
+}
+
 hipError_t combine_launch(const BwdArgs& a, hipStream_t s) {
-  const int shared_v = (a.d_verts != nullptr) && !a.per_env;
-  long long nv = 0;
-  for (int m = 0; m < a.n_meshes; ++m) nv += a.meshes[m].n;
-  const int pose_blocks = (a.n_env + 3) / 4;
-  const long long vert_blocks = shared_v ? (3 * nv + 255) / 256 : 0;
-  hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)(pose_blocks + vert_blocks)), dim3(256), 0, s, a, shared_v, nv,
-                     pose_blocks);
+  const CombineShape c = combine_shape(a);
+  hipLaunchKernelGGL(k_bwd_combine, dim3((unsigned)(c.pose_blocks + c.vert_blocks)), dim3(256), 0, s, a, c.shared_v,
+                     c.nv, c.pose_blocks);
   return hipGetLastError();
 }
 
@@ -1078,10 +1145,11 @@ hipError_t qbwd_launch(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, 
   if (e != hipSuccess) return e;
   e = mark(true, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_payload<DT, LAYOUT>), dim3((f.n_env + 3) / 4), dim3(256), 0, s, f, 0);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return combine_launch(a, s);
+  const CombineShape c = combine_shape(a);
+  const int payload_blocks = (f.n_env + 3) / 4;
+  hipLaunchKernelGGL((k_tail<DT, LAYOUT>), dim3((unsigned)(payload_blocks + c.pose_blocks + c.vert_blocks)),
+                     dim3(256), 0, s, f, a, c.shared_v, c.nv, c.pose_blocks, payload_blocks);
+  return hipGetLastError();
 }
 
 template <int DT, int LAYOUT>
@@ -1099,6 +1167,26 @@ hipError_t probe_layout(const BwdArgs& a, int layout, hipStream_t s) {
   if (layout == FC_LAYOUT_BRICK) return probe_launch<DT, FC_LAYOUT_BRICK>(a, s);
   if (layout == FC_LAYOUT_SLAB) return probe_launch<DT, FC_LAYOUT_SLAB>(a, s);
   return probe_launch<DT, FC_LAYOUT_LINEAR>(a, s);
+}
+
+template <int DT, int LAYOUT>
+hipError_t qchunk_launch(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, hipStream_t s) {
+  hipError_t e = mark(false, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_query_chunked<DT, LAYOUT>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a, q);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = mark(true, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_payload<DT, LAYOUT>), dim3((f.n_env + 3) / 4), dim3(256), 0, s, f, 0);
+  return hipGetLastError();
+}
+
+template <int DT>
+hipError_t qchunk_layout(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, int layout, hipStream_t s) {
+  if (layout == FC_LAYOUT_BRICK) return qchunk_launch<DT, FC_LAYOUT_BRICK>(a, q, f, s);
+  if (layout == FC_LAYOUT_SLAB) return qchunk_launch<DT, FC_LAYOUT_SLAB>(a, q, f, s);
+  return qchunk_launch<DT, FC_LAYOUT_LINEAR>(a, q, f, s);
 }
 
 template <int DT>
@@ -1157,6 +1245,7 @@ bool forward_shape_supported(int block, int vpt) {
 
 hipError_t launch_forward(const FwdArgs& a, int dtype, int layout, int block, int vpt, int persistent, int xcd,
                           int grid, bool from_cand, hipStream_t s, const KernelMarks* m) {
+  if (persistent < 0 || persistent > 2) return hipErrorInvalidValue;  // k_forward's own modes only
   if (grid <= 0) return hipSuccess;
   const MarksScope scope(m);
   // the reduction-from-candidates pass never reads the grid: one instantiation serves every dtype
@@ -1183,6 +1272,18 @@ hipError_t launch_query_backward(const BwdArgs& a, const QueryExtra& q, const Fw
     case kF32: return qbwd_layout<kF32>(a, q, payload, layout, s);
     case kF16: return qbwd_layout<kF16>(a, q, payload, layout, s);
     case kBF16: return qbwd_layout<kBF16>(a, q, payload, layout, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_query_chunked(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,
+                                hipStream_t s, const KernelMarks* m) {
+  if (a.n_items <= 0) return hipSuccess;
+  const MarksScope scope(m);
+  switch (dtype) {
+    case kF32: return qchunk_layout<kF32>(a, q, payload, layout, s);
+    case kF16: return qchunk_layout<kF16>(a, q, payload, layout, s);
+    case kBF16: return qchunk_layout<kBF16>(a, q, payload, layout, s);
   }
   return hipErrorInvalidValue;
 }

@@ -129,9 +129,11 @@ def test_autotune_cache_parse(L, tmp_path):
     p.write_text(json.dumps({"entries": [
         {"key": "a", "block": 256, "tile": 1024, "persistent": 0, "grid_mult": 8},
         {"key": "b", "block": 128, "tile": 512, "persistent": 2, "grid_mult": 4},
+        {"key": "c", "block": 256, "tile": 1024, "persistent": 3, "grid_mult": 8, "xcd_remap": 1},
         {"key": "bad", "block": 100, "tile": 1024, "persistent": 0, "grid_mult": 8},
+        {"key": "bad2", "block": 256, "tile": 1024, "persistent": 4, "grid_mult": 8},
     ]}))
-    assert L.fc_autotune_load(str(p).encode()) == 2
+    assert L.fc_autotune_load(str(p).encode()) == 3
     p.write_text("{not json")
     assert L.fc_autotune_load(str(p).encode()) == -1
     assert L.fc_autotune_load(b"/nonexistent/file.json") == -1

@@ -119,6 +119,27 @@ def test_launch_shapes_bit_identical(nutbolt24, shape):
         b.set_launch(**old)
 
 
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_env_chunked_forward_bit_identical(nutbolt24, torus, xcd):
+    """persistent = 3: the fused forward on the adjoint's env-chunked items
+    gives the contacts of the per-item kernel, bit for bit, call after call."""
+    for w, b, pose in (nutbolt24, torus):
+        _, ref = run(b, pose, cand=False)
+        old = b.get_launch()
+        try:
+            b.set_launch(**dict(old, persistent=3, xcd_remap=xcd))
+            for _ in range(2):
+                _, o = run(b, pose, cand=False)
+                assert_same(o, ref)
+            c, o = run(b, pose)  # with candidates requested the per-item kernel runs
+            assert_same(o, ref)
+            for _ in range(2):  # candidates alone, then the reduction: per-item kernel, plain launches
+                c, o = run_unfused(b, pose)
+                assert_same(o, ref)
+        finally:
+            b.set_launch(**old)
+
+
 def test_env_order_does_not_change_contacts(nutbolt24):
     w, b, pose = nutbolt24
     ref_c, ref_o = run(b, pose)
