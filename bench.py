@@ -164,6 +164,62 @@ def depth_check(w, cand_phi, n_env=4):
     return float(np.max(np.abs(phi[ins] - o["phi"][ins])))
 
 
+def time_calls(fn, n, warmup):
+    """Mean wall time per call (ms) of n calls between two synchronisations."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / n
+
+
+def measure_forms(w32, device, n, warmup):
+    """The other forms of the path beside the FP32 nut-bolt step: the same
+    batch with FP16 and BF16 grid storage, and the uneven mixed batch
+    (4,096 envs, five part types) replayed as hipGraphs.  Queries/s of the
+    one-pass step and of the fused forward; depth error of the half forms
+    against the FP64 oracle on the FP32 grid (4 envs)."""
+    import torch
+
+    from paper_2205_03532_amd import fc
+    from paper_2205_03532_amd import workloads as W
+
+    out = {}
+    for dt in ("f16", "bf16"):
+        wh = W.half_storage(w32, dt)
+        b = make_batch(wh, device)
+        pose = fc.pose_tensor(wh.pose, device)
+        o, g = b.new_contacts(), b.new_grads(per_env=False)
+        ms_one = time_calls(lambda: fc.fc_sdf_query_and_backward(b, pose, o, K_PENALTY, g), n, warmup)
+        ms_fwd = time_calls(lambda: fc.fc_sdf_query(b, pose, fused_out=o), n, warmup)
+        cand = b.new_candidates()
+        fc.fc_sdf_query(b, pose, cand=cand)
+        torch.cuda.synchronize()
+        out[f"nutbolt_{dt}_grid"] = {
+            "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3), "fwd_queries_per_s": b.Q / (ms_fwd * 1e-3),
+            "alg_bytes_per_query": alg_bytes_per_query(dt),
+            "max_depth_err_m_vs_fp32_grid_oracle": depth_check(w32, cand["phi"].cpu().numpy()),
+            "launch": b.get_launch()}
+        del b, o, g, cand
+    wm = W.mixed_workload()
+    b = make_batch(wm, device)
+    pose = fc.pose_tensor(wm.pose, device)
+    o, g = b.new_contacts(), b.new_grads(per_env=False)
+    g_one = fc.fc_graph_create(b, pose, fused_out=o, k=K_PENALTY, grads=g)
+    g_fwd = fc.fc_graph_create(b, pose, fused_out=o)
+    ms_one = time_calls(g_one.launch, n, warmup)
+    ms_fwd = time_calls(g_fwd.launch, n, warmup)
+    out["mixed_4096_envs_5_types_graph"] = {
+        "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3), "fwd_queries_per_s": b.Q / (ms_fwd * 1e-3),
+        "queries_per_step": b.Q, "launch": b.get_launch()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +230,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--cpu-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 and mixed-batch measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates rocprof byte counters) and exit")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -353,6 +410,8 @@ def main():
             },
         },
     }
+    if not args.no_forms and args.dtype == "f32":
+        res["forms"] = measure_forms(w, dev, n, args.warmup)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, w.n_env))
     print(json.dumps(res), flush=True)
