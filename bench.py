@@ -178,6 +178,27 @@ def time_calls(fn, n, warmup):
     return (time.perf_counter() - t0) * 1e3 / n
 
 
+def measure_faces(batch, pose, n, warmup):
+    """Per-face contact generation on the bench batch (fc_sdf_query_faces, fused
+    reduction): faces per second, and the main kernel's time."""
+    import torch
+
+    from paper_2205_03532_amd import fc
+
+    o = batch.new_contacts()
+    call = lambda: fc.fc_sdf_query_faces(batch, pose, fused_out=o)
+    ms = time_calls(call, n, warmup)
+    batch.set_timing(n)
+    for _ in range(n):
+        call()
+    k, _ = batch.read_timing()
+    batch.set_timing(0)
+    torch.cuda.synchronize()
+    return {"faces_per_s": batch.Qf / (ms * 1e-3), "faces_per_call": batch.Qf, "call_ms": ms,
+            "k_faces_ms": float(k.mean()), "iters": fc.PGD_ITERS, "step0": fc.PGD_STEP0,
+            "samples_per_face": fc.PGD_ITERS + 1}
+
+
 def measure_forms(w32, device, n, warmup):
     """The other forms of the path beside the FP32 nut-bolt step: the same
     batch with FP16 and BF16 grid storage, and the uneven mixed batch
@@ -411,7 +432,8 @@ def main():
         },
     }
     if not args.no_forms and args.dtype == "f32":
-        res["forms"] = measure_forms(w, dev, n, args.warmup)
+        res["forms"] = {"nutbolt_faces_pgd": measure_faces(batch, pose, n, args.warmup)}
+        res["forms"].update(measure_forms(w, dev, n, args.warmup))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, w.n_env))
     print(json.dumps(res), flush=True)

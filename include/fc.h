@@ -88,12 +88,18 @@ typedef struct fc_grid {
   float h;          /* node spacing, > 0, metres */
 } fc_grid;
 
-/* Body A: the queried mesh's vertices in A's frame, SoA (device). */
+/* Body A: the queried mesh's vertices in A's frame, SoA (device), and
+ * optionally its triangles for per-face queries (fc_sdf_query_faces):
+ * tris = device [3][n_tris] vertex indices (corner a of every face, then b,
+ * then c), NULL when n_tris = 0.  A face with an index outside
+ * [0, n_verts) is never a candidate. */
 typedef struct fc_mesh {
   const float* x;
   const float* y;
   const float* z;
   int32_t n_verts; /* >= 0 (an empty mesh gives empty contact lists) */
+  const int32_t* tris;
+  int32_t n_tris; /* >= 0 */
 } fc_mesh;
 
 /* Static description of a batch of independent environments (shape pairs).
@@ -123,11 +129,15 @@ typedef struct fc_batch fc_batch; /* opaque; owns device work tables */
 /* Per-query candidates (Algorithm 1, Generate), all device, index q:
  *   phi[q]      trilinear SDF value at x_B, or +inf when x_B is outside the grid;
  *   normal      [3][Q]: grad(phi)/|grad(phi)|, (0,0,0) for a zero gradient or outside;
- *   bin[q]      argmax_k normal.d_k (lowest k on ties) when phi < margin, else -1. */
+ *   bin[q]      argmax_k normal.d_k (lowest k on ties) when phi < margin, else -1;
+ *   point       [3][Q] the query point in B's frame, per-face queries only
+ *               (fc_sdf_query_faces: the descent's final point); ignored by
+ *               the vertex calls, which may leave it NULL. */
 typedef struct fc_candidates {
   float* phi;
   float* normal;
   int16_t* bin;
+  float* point;
 } fc_candidates;
 
 /* Reduced contacts, one slot per (environment, bin), slot s = e*K + k (device).
@@ -244,6 +254,37 @@ fc_status fc_contact_reduce(const fc_batch* batch, const float* pose, const fc_c
 fc_status fc_sdf_query_backward(const fc_batch* batch, const float* pose, float k, const float* upstream,
                                 const fc_grads* out, void* ws, size_t ws_bytes, void* stream);
 
+/* Per-face contact generation (Section III-A: one contact per triangle of
+ * A's mesh, at the point of the face that minimises B's SDF, found by
+ * projected gradient descent with an adaptive step).  For every environment
+ * e and face f of its mesh: corners x_i = R(q_e) v_i + t_e; start at the
+ * centroid b = (1/3, 1/3, 1/3); each of pgd->iters trials takes
+ * b' = P(b - alpha (0, g.e1, g.e2)) (P the Euclidean projection onto the
+ * simplex, g the SDF gradient at the current point, e1 = x_b - x_a,
+ * e2 = x_c - x_a) and keeps it iff phi decreases strictly (a trial outside
+ * the grid never does), alpha doubling after a kept trial and halving after
+ * a rejected one; alpha starts at pgd->step0 / sqrt(S), S the sum of squared
+ * corner distances to the centroid (0 for a degenerate face).  The final
+ * point is the face's candidate, recorded and binned as a vertex query's
+ * (phi < margin; depth = -phi; normal; bin) and reduced per (env, bin) with
+ * the face index as tie-break (contacts' vidx holds the face index).
+ *   pgd        iters in [0, 64], step0 finite and > 0;
+ *   cand       NULL, or per-face candidates indexed q = face offset of e + f
+ *              (fc_batch_face_queries entries; phi, normal, bin and point);
+ *   fused_out  NULL, or the reduced contacts.
+ * At least one of cand / fused_out must be non-NULL.  Meshes without
+ * triangles give no face contacts.  Workspace as for fc_sdf_query. */
+typedef struct fc_pgd {
+  int32_t iters;
+  float step0;
+} fc_pgd;
+fc_status fc_sdf_query_faces(const fc_batch* batch, const float* pose, const fc_pgd* pgd,
+                             const fc_candidates* cand, const fc_contacts* fused_out, void* ws, size_t ws_bytes,
+                             void* stream);
+/* Number of per-face queries of a batch (sum over envs of their mesh's
+ * n_tris), or -1 for NULL. */
+int64_t fc_batch_face_queries(const fc_batch* batch);
+
 /* fc_sdf_query with fused_out, then fc_sdf_query_backward, computed in one
  * pass over the queries: each query is located, gathered and interpolated
  * once and feeds both the contact reduction and the penalty adjoint.  Every
@@ -297,7 +338,8 @@ int32_t fc_batch_signature(const fc_batch* batch, char* buf, int32_t cap);
 
 /* Per-launch timing of the main kernels.  After fc_batch_set_timing(batch, n)
  * the next n compute calls on this batch (fc_sdf_query, fc_contact_reduce,
- * fc_sdf_query_backward, fc_sdf_query_and_backward; not graph capture or
+ * fc_sdf_query_backward, fc_sdf_query_and_backward, fc_sdf_query_faces,
+ * fc_gather_probe; not graph capture or
  * replay) record a pair of HIP events on their stream right before and right
  * after their main kernel, leaving out the small payload / combine kernels
  * that follow it.  n = 0 turns timing off; 0 <= n <= FC_MAX_TIMING_RECORDS
@@ -308,7 +350,8 @@ typedef enum fc_kernel_id {
   FC_KERNEL_FORWARD = 0,        /* k_forward (any mode) */
   FC_KERNEL_BACKWARD = 1,       /* k_backward */
   FC_KERNEL_QUERY_BACKWARD = 2, /* k_query_backward */
-  FC_KERNEL_GATHER_PROBE = 3    /* k_gather_probe */
+  FC_KERNEL_GATHER_PROBE = 3,   /* k_gather_probe */
+  FC_KERNEL_FACES = 4           /* k_faces */
 } fc_kernel_id;
 fc_status fc_batch_set_timing(fc_batch* batch, int32_t max_records);
 /* Waits for the recorded launches and writes, for the first min(recorded,

@@ -89,8 +89,9 @@ fc_status validate_desc(const fc_batch_desc* d) {
   }
   for (int i = 0; i < d->n_meshes; ++i) {
     const fc_mesh& m = d->meshes[i];
-    if (m.n_verts < 0) return FC_ERR_SHAPE;
+    if (m.n_verts < 0 || m.n_tris < 0) return FC_ERR_SHAPE;
     if (m.n_verts > 0 && (!m.x || !m.y || !m.z)) return FC_ERR_NULL;
+    if (m.n_tris > 0 && !m.tris) return FC_ERR_NULL;
   }
   if (d->env_order) {
     std::vector<char> seen(d->n_env, 0);
@@ -361,6 +362,11 @@ struct fc_batch {
   Item* d_items = nullptr;
   int n_items = 0;
   EnvInfo* d_envs = nullptr;
+  // per-face tables: (env, face tile) items in scheduling order, face query offsets
+  Item* d_fitems = nullptr;
+  int n_fitems = 0;
+  EnvInfo* d_fenvs = nullptr;
+  long long Qf = 0;
   // backward tables
   BwdItem* d_bitems = nullptr;
   int n_bitems = 0;
@@ -392,6 +398,10 @@ void free_tables(fc_batch* b) {
   if (b->d_chunks) (void)hipFree(b->d_chunks);
   if (b->d_env_list) (void)hipFree(b->d_env_list);
   if (b->d_env_tile_base) (void)hipFree(b->d_env_tile_base);
+  if (b->d_fitems) (void)hipFree(b->d_fitems);
+  if (b->d_fenvs) (void)hipFree(b->d_fenvs);
+  b->d_fitems = nullptr;
+  b->d_fenvs = nullptr;
   b->d_items = nullptr;
   b->d_envs = nullptr;
   b->d_bitems = nullptr;
@@ -467,6 +477,37 @@ int choose_bwd_chunk(const fc_batch* b, const std::vector<std::vector<int>>& gro
     if (items <= capacity) return c;
   }
   return kBwdChunkMax;
+}
+
+fc_status build_face_tables(fc_batch* b) {
+  std::vector<Item> items;
+  std::vector<EnvInfo> envs(b->n_env);
+  long long q = 0;
+  for (int e = 0; e < b->n_env; ++e) {
+    envs[e].qoff = q;
+    envs[e].gm = gm_of(b, e);
+    envs[e].n_items = 0;
+    q += b->meshes[b->env_mesh[e]].n_tris;
+  }
+  b->Qf = q;
+  for (int oi = 0; oi < b->n_env; ++oi) {
+    const int e = b->order[oi];
+    const int nt = b->meshes[b->env_mesh[e]].n_tris;
+    for (int t0 = 0; t0 < nt; t0 += kFaceTile) {
+      Item it;
+      it.env = e;
+      it.vstart = t0;
+      it.vcount = std::min(kFaceTile, nt - t0);
+      it.gm = gm_of(b, e);
+      items.push_back(it);
+      ++envs[e].n_items;
+    }
+  }
+  b->n_fitems = (int)items.size();
+  fc_status s = FC_OK;
+  if (!items.empty()) s = upload(&b->d_fitems, items);
+  if (s == FC_OK) s = upload(&b->d_fenvs, envs);
+  return s;
 }
 
 fc_status build_backward_tables(fc_batch* b) {
@@ -574,7 +615,8 @@ void fill_common(const fc_batch* b, GridDev* grids, MeshDev* meshes) {
     meshes[i].y = b->meshes[i].y;
     meshes[i].z = b->meshes[i].z;
     meshes[i].n = b->meshes[i].n_verts;
-    meshes[i].pad = 0;
+    meshes[i].tris = b->meshes[i].tris;
+    meshes[i].nt = b->meshes[i].n_tris;
   }
 }
 
@@ -794,6 +836,7 @@ fc_status fc_batch_create(const fc_batch_desc* desc, fc_batch** out) {
   s = upload(&b->d_lut, build_bin_lut(b->dirs, b->K));
   if (s == FC_OK) s = build_forward_tables(b);
   if (s == FC_OK) s = build_backward_tables(b);
+  if (s == FC_OK) s = build_face_tables(b);
   if (s != FC_OK) {
     free_tables(b);
     delete b;
@@ -919,6 +962,35 @@ fc_status fc_sdf_query_and_backward(const fc_batch* b, const float* pose, const 
   if (s != FC_OK) return s;
   return enqueue_query_backward(b, pose, fused_out, k, upstream, grads, ws, (hipStream_t)stream, true);
 }
+
+fc_status fc_sdf_query_faces(const fc_batch* b, const float* pose, const fc_pgd* pgd, const fc_candidates* cand,
+                             const fc_contacts* fused_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!b || !pose || !pgd) return FC_ERR_NULL;
+  if (!cand && !fused_out) return FC_ERR_NULL;
+  if (cand && (!cand->phi || !cand->normal || !cand->bin || !cand->point)) return FC_ERR_NULL;
+  if (fused_out && !contacts_ok(fused_out)) return FC_ERR_NULL;
+  if (pgd->iters < 0 || pgd->iters > 64 || !(pgd->step0 > 0.f) || !std::isfinite(pgd->step0)) return FC_ERR_RANGE;
+  fc_status s = check_ws(b, ws, ws_bytes);
+  if (s != FC_OK) return s;
+  FwdArgs a = make_fwd(b, pose, nullptr, fused_out, ws);
+  a.items = b->d_fitems;
+  a.n_items = b->n_fitems;
+  a.envs = b->d_fenvs;
+  a.Q = b->Qf;
+  if (cand) {
+    a.c_phi = cand->phi;
+    a.c_nrm = cand->normal;
+    a.c_bin = cand->bin;
+    a.c_point = cand->point;
+  }
+  a.pgd_iters = pgd->iters;
+  a.pgd_step0 = pgd->step0;
+  KernelMarks m;
+  FC_HIP(launch_faces(a, b->dtype, b->layout, (hipStream_t)stream, take_marks(b, FC_KERNEL_FACES, true, m)));
+  return FC_OK;
+}
+
+int64_t fc_batch_face_queries(const fc_batch* b) { return b ? b->Qf : -1; }
 
 fc_status fc_gather_probe(const fc_batch* b, const float* pose, float* sink, void* stream) {
   if (!b || !pose || !sink) return FC_ERR_NULL;

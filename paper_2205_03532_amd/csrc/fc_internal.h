@@ -66,8 +66,9 @@ struct MeshDev {
   const float* x;
   const float* y;
   const float* z;
+  const int* tris;  // [3][nt] corner indices (per-face queries), or null
   int n;
-  int pad;
+  int nt;
 };
 
 struct Item {  // one forward work item: a tile of one environment's vertices
@@ -100,6 +101,10 @@ struct FwdArgs {
   float* c_phi;
   float* c_nrm;
   int16_t* c_bin;
+  float* c_point;  // per-face queries only
+  // per-face queries: descent trials and first step
+  int pgd_iters;
+  float pgd_step0;
   // reduced contacts (may be null)
   int* o_vidx;
   float* o_depth;
@@ -185,6 +190,12 @@ hipError_t launch_backward(const BwdArgs& a, int dtype, int layout, hipStream_t 
 // outputs and keys) and the adjoint's combine
 hipError_t launch_query_backward(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,
                                  hipStream_t s, const KernelMarks* m);
+// per-face queries: k_faces over (env, face tile) items, then k_face_payload
+hipError_t launch_faces(const FwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m);
+constexpr int kFaceBlock = 256;  // threads per face workgroup
+constexpr int kFaceVpt = 2;      // faces per thread (independent descents interleaved)
+constexpr int kFaceTile = kFaceBlock * kFaceVpt;
+
 // the fused forward on the adjoint's env-chunked work items (fc_launch
 // persistent = 3): k_query_chunked, then the payload
 hipError_t launch_query_chunked(const BwdArgs& a, const QueryExtra& q, const FwdArgs& payload, int dtype, int layout,

@@ -569,6 +569,239 @@ __global__ __launch_bounds__(256) void k_payload(FwdArgs A, int from_cand) {
 }
 
 // ---------------------------------------------------------------------------
+// per-face queries: projected gradient descent of phi over each face
+// ---------------------------------------------------------------------------
+// Euclidean projection of (y0, y1, y2) onto the simplex {b >= 0, sum b = 1}:
+// with u the values sorted in decreasing order and c_j = u_1 + ... + u_j - 1,
+// rho counts the j with u_j > c_j / j (they form a prefix) and the threshold
+// is theta = c_rho / rho.
+__device__ __forceinline__ void project_simplex3(float y0, float y1, float y2, float& b0, float& b1, float& b2) {
+  float u0 = y0, u1 = y1, u2 = y2;
+  if (u0 < u1) { const float t = u0; u0 = u1; u1 = t; }
+  if (u1 < u2) { const float t = u1; u1 = u2; u2 = t; }
+  if (u0 < u1) { const float t = u0; u0 = u1; u1 = t; }
+  const float c1 = u0 - 1.f;
+  const float c2 = (u0 + u1) - 1.f;
+  const float c3 = ((u0 + u1) + u2) - 1.f;
+  const int rho = 1 + ((u1 - c2 * 0.5f) > 0.f ? 1 : 0) + ((u2 - c3 * (1.f / 3.f)) > 0.f ? 1 : 0);
+  const float theta = rho == 1 ? c1 : (rho == 2 ? c2 * 0.5f : c3 * (1.f / 3.f));
+  b0 = fmaxf(y0 - theta, 0.f);
+  b1 = fmaxf(y1 - theta, 0.f);
+  b2 = fmaxf(y2 - theta, 0.f);
+}
+
+// One face's descent state: first corner and edges in B's frame, barycentric
+// coordinates, the current point, phi there (+inf outside the grid) and its
+// grid-unit gradient, the step.
+struct FaceState {
+  float ax, ay, az, e1x, e1y, e1z, e2x, e2y, e2z;
+  float b1, b2;  // b0 = 1 - b1 - b2 is carried by the projection
+  float b0;
+  float x, y, z;
+  float phi, gx, gy, gz;
+  float alpha;
+  bool valid;
+};
+
+__device__ __forceinline__ void face_point(const FaceState& S, float b1, float b2, float& x, float& y, float& z) {
+  x = fmaf(b2, S.e2x, fmaf(b1, S.e1x, S.ax));
+  y = fmaf(b2, S.e2y, fmaf(b1, S.e1y, S.ay));
+  z = fmaf(b2, S.e2z, fmaf(b1, S.e1z, S.az));
+}
+
+// Descent of NV faces at once (their loads interleaved): corners from the
+// mesh (a face with an out-of-range index is marked invalid and never
+// accepts a trial), start at the centroid, iters projected trials with the
+// accept-if-lower rule and a doubling / halving step.
+template <int DT, int LAYOUT, int NV>
+__device__ __forceinline__ void face_descent(const GridDev& g, const MeshDev& m, const Rigid& P, const int (&f)[NV],
+                                             const bool (&ok)[NV], int iters, float step0, FaceState (&S)[NV]) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    FaceState& F = S[j];
+    unsigned ia = 0, ib = 0, ic = 0;
+    if (ok[j]) {
+      ia = (unsigned)m.tris[f[j]];
+      ib = (unsigned)m.tris[m.nt + f[j]];
+      ic = (unsigned)m.tris[2 * m.nt + f[j]];
+    }
+    F.valid = ok[j] & (ia < (unsigned)m.n) & (ib < (unsigned)m.n) & (ic < (unsigned)m.n);
+    if (!F.valid) ia = ib = ic = 0;
+    float bx, by, bz, cx, cy, cz;
+    const bool any_v = m.n > 0;
+    transform(P, any_v ? m.x[ia] : 0.f, any_v ? m.y[ia] : 0.f, any_v ? m.z[ia] : 0.f, F.ax, F.ay, F.az);
+    transform(P, any_v ? m.x[ib] : 0.f, any_v ? m.y[ib] : 0.f, any_v ? m.z[ib] : 0.f, bx, by, bz);
+    transform(P, any_v ? m.x[ic] : 0.f, any_v ? m.y[ic] : 0.f, any_v ? m.z[ic] : 0.f, cx, cy, cz);
+    F.e1x = bx - F.ax; F.e1y = by - F.ay; F.e1z = bz - F.az;
+    F.e2x = cx - F.ax; F.e2y = cy - F.ay; F.e2z = cz - F.az;
+    const float dx = F.e2x - F.e1x, dy = F.e2y - F.e1y, dz = F.e2z - F.e1z;
+    const float S3 = fmaf(F.e1x, F.e1x, fmaf(F.e1y, F.e1y, F.e1z * F.e1z)) +
+                     fmaf(F.e2x, F.e2x, fmaf(F.e2y, F.e2y, F.e2z * F.e2z)) + fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float SS = S3 * (1.f / 3.f);  // sum of squared corner distances to the centroid
+    F.alpha = SS > 0.f ? step0 * rsqrtf(SS) : 0.f;
+    F.b0 = F.b1 = F.b2 = 1.f / 3.f;
+    face_point(F, F.b1, F.b2, F.x, F.y, F.z);
+  }
+  Cell cl[NV];
+  float cc[NV][8];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) cl[j] = locate(g, S[j].x, S[j].y, S[j].z);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) gather<DT, LAYOUT>(g, cl[j], cc[j]);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    float phi, gx, gy, gz;
+    trilinear(cc[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
+    S[j].phi = (S[j].valid & cl[j].inside) ? phi : __builtin_inff();
+    S[j].gx = gx;
+    S[j].gy = gy;
+    S[j].gz = gz;
+  }
+  for (int it = 0; it < iters; ++it) {
+    float tb0[NV], tb1[NV], tb2[NV], tx[NV], ty[NV], tz[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const FaceState& F = S[j];
+      // b-gradient (0, g.e1, g.e2) with g in metres (grid units / h)
+      const float d1 = g.inv_h * fmaf(F.gx, F.e1x, fmaf(F.gy, F.e1y, F.gz * F.e1z));
+      const float d2 = g.inv_h * fmaf(F.gx, F.e2x, fmaf(F.gy, F.e2y, F.gz * F.e2z));
+      project_simplex3(F.b0, fmaf(-F.alpha, d1, F.b1), fmaf(-F.alpha, d2, F.b2), tb0[j], tb1[j], tb2[j]);
+      face_point(F, tb1[j], tb2[j], tx[j], ty[j], tz[j]);
+      cl[j] = locate(g, tx[j], ty[j], tz[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) gather<DT, LAYOUT>(g, cl[j], cc[j]);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      FaceState& F = S[j];
+      float phi, gx, gy, gz;
+      trilinear(cc[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
+      const bool keep = F.valid & cl[j].inside & (phi < F.phi);
+      if (keep) {
+        F.b0 = tb0[j];
+        F.b1 = tb1[j];
+        F.b2 = tb2[j];
+        F.x = tx[j];
+        F.y = ty[j];
+        F.z = tz[j];
+        F.phi = phi;
+        F.gx = gx;
+        F.gy = gy;
+        F.gz = gz;
+      }
+      F.alpha = keep ? 2.f * F.alpha : 0.5f * F.alpha;
+    }
+  }
+}
+
+// One work item: a tile of kFaceTile faces of one environment.  Candidates,
+// bins and the per-bin maxima as in query_item, keyed by the face index.
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(kFaceBlock) void k_faces(FwdArgs A) {
+  __shared__ unsigned long long s_keys[FC_MAX_BINS];
+  __shared__ BinCell s_lut[kLutCells];
+  __shared__ float4 s_dir4[FC_MAX_BINS];
+  static_assert(sizeof(BinCell) == sizeof(uint4), "BinCell is one 16-byte load");
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(A.bin_lut);
+    uint4* dst = reinterpret_cast<uint4*>(s_lut);
+    for (int i = threadIdx.x; i < kLutCells; i += kFaceBlock) dst[i] = src[i];
+  }
+  if (threadIdx.x < FC_MAX_BINS) {
+    const int k = threadIdx.x < A.K ? threadIdx.x : 0;
+    s_dir4[threadIdx.x] = make_float4(A.dirs[k], A.dirs[A.K + k], A.dirs[2 * A.K + k], 0.f);
+    s_keys[threadIdx.x] = 0ull;
+  }
+  __syncthreads();
+  const Item it = A.items[blockIdx.x];
+  const GridDev& g = A.grids[it.gm & 0xff];
+  const MeshDev& m = A.meshes[it.gm >> 8];
+  const Rigid P = load_pose(A.pose, A.n_env, it.env);
+  const bool fused = A.o_vidx != nullptr;
+  const bool want_cand = A.c_phi != nullptr;
+  const long long qoff = A.envs[it.env].qoff;
+  int f[kFaceVpt];
+  bool ok[kFaceVpt];
+#pragma unroll
+  for (int j = 0; j < kFaceVpt; ++j) {
+    f[j] = it.vstart + j * kFaceBlock + (int)threadIdx.x;
+    ok[j] = f[j] < it.vstart + it.vcount;
+  }
+  FaceState S[kFaceVpt];
+  face_descent<DT, LAYOUT, kFaceVpt>(g, m, P, f, ok, A.pgd_iters, A.pgd_step0, S);
+#pragma unroll
+  for (int j = 0; j < kFaceVpt; ++j) {
+    const FaceState& F = S[j];
+    const bool inside = F.phi < __builtin_inff();
+    const bool cand = inside & (F.phi < A.margin);
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    int bin = -1;
+    if (cand | (want_cand & inside)) normalize(F.gx, F.gy, F.gz, nx, ny, nz);
+    if (cand) bin = argmax_bin_lut(s_lut, s_dir4, A.dirs, A.K, nx, ny, nz);
+    if (want_cand & ok[j]) {
+      const long long q = qoff + f[j];
+      A.c_phi[q] = F.phi;
+      A.c_nrm[q] = nx;
+      A.c_nrm[A.Q + q] = ny;
+      A.c_nrm[2 * A.Q + q] = nz;
+      A.c_bin[q] = (int16_t)bin;
+      A.c_point[q] = F.x;
+      A.c_point[A.Q + q] = F.y;
+      A.c_point[2 * A.Q + q] = F.z;
+    }
+    if (fused) bin_max(cand, bin, make_key(-F.phi, (unsigned)f[j]), s_keys);
+  }
+  if (fused) {
+    __syncthreads();
+    if ((int)threadIdx.x < A.K) {
+      const unsigned long long k = s_keys[threadIdx.x];
+      if (k) atomicMax(&A.keys[(long long)it.env * A.K + threadIdx.x], k);
+    }
+  }
+}
+
+// Winners of the per-face query: one wavefront per environment, lane = bin;
+// the winning face's descent is run again (same arithmetic, same bits) for
+// its point and normal.  Takes each key, resetting it to zero.
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(256) void k_face_payload(FwdArgs A) {
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= A.n_env) return;
+  unsigned long long key = 0ull;
+  if (lane < A.K) {
+    unsigned long long* kp = A.keys + (long long)e * A.K + lane;
+    key = *kp;
+    *kp = 0ull;
+  }
+  const int gm = A.envs[e].gm;
+  const MeshDev& m = A.meshes[gm >> 8];
+  const unsigned fv = key_vidx(key);
+  const bool have = (lane < A.K) && (key != 0ull) && (fv < (unsigned)m.nt);
+  const int f[1] = {have ? (int)fv : 0};
+  const bool ok[1] = {have};
+  FaceState S[1];
+  face_descent<DT, LAYOUT, 1>(A.grids[gm & 0xff], m, load_pose(A.pose, A.n_env, e), f, ok, A.pgd_iters,
+                              A.pgd_step0, S);
+  if (lane < A.K) {
+    const long long NS = (long long)A.n_env * A.K;
+    const long long s = (long long)e * A.K + lane;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    if (have) normalize(S[0].gx, S[0].gy, S[0].gz, nx, ny, nz);
+    A.o_vidx[s] = have ? (int)fv : -1;
+    A.o_depth[s] = have ? key_depth(key) : 0.f;
+    A.o_point[s] = have ? S[0].x : 0.f;
+    A.o_point[NS + s] = have ? S[0].y : 0.f;
+    A.o_point[2 * NS + s] = have ? S[0].z : 0.f;
+    A.o_nrm[s] = nx;
+    A.o_nrm[NS + s] = ny;
+    A.o_nrm[2 * NS + s] = nz;
+  }
+  const unsigned long long nonempty = __ballot(have);
+  if (lane == 0) A.o_count[e] = __popcll(nonempty);
+}
+
+// ---------------------------------------------------------------------------
 // adjoint of the penetration penalty
 // ---------------------------------------------------------------------------
 // Neumaier compensated accumulation, (sum, compensation) in a float2.
@@ -1284,6 +1517,41 @@ hipError_t launch_query_chunked(const BwdArgs& a, const QueryExtra& q, const Fwd
     case kF32: return qchunk_layout<kF32>(a, q, payload, layout, s);
     case kF16: return qchunk_layout<kF16>(a, q, payload, layout, s);
     case kBF16: return qchunk_layout<kBF16>(a, q, payload, layout, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DT, int LAYOUT>
+hipError_t faces_launch(const FwdArgs& a, hipStream_t s) {
+  hipError_t e = mark(false, s);
+  if (e != hipSuccess) return e;
+  if (a.n_items > 0) {  // none when no env's mesh has faces: the payload still writes empty lists
+    hipLaunchKernelGGL((k_faces<DT, LAYOUT>), dim3(a.n_items), dim3(kFaceBlock), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  e = mark(true, s);
+  if (e != hipSuccess) return e;
+  if (a.o_vidx) {
+    hipLaunchKernelGGL((k_face_payload<DT, LAYOUT>), dim3((a.n_env + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+template <int DT>
+hipError_t faces_layout(const FwdArgs& a, int layout, hipStream_t s) {
+  if (layout == FC_LAYOUT_BRICK) return faces_launch<DT, FC_LAYOUT_BRICK>(a, s);
+  if (layout == FC_LAYOUT_SLAB) return faces_launch<DT, FC_LAYOUT_SLAB>(a, s);
+  return faces_launch<DT, FC_LAYOUT_LINEAR>(a, s);
+}
+
+hipError_t launch_faces(const FwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m) {
+  const MarksScope scope(m);
+  switch (dtype) {
+    case kF32: return faces_layout<kF32>(a, layout, s);
+    case kF16: return faces_layout<kF16>(a, layout, s);
+    case kBF16: return faces_layout<kBF16>(a, layout, s);
   }
   return hipErrorInvalidValue;
 }

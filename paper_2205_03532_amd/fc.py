@@ -17,7 +17,7 @@ import os
 
 import numpy as np
 
-FC_KERNEL_FORWARD, FC_KERNEL_BACKWARD, FC_KERNEL_QUERY_BACKWARD, FC_KERNEL_GATHER_PROBE = 0, 1, 2, 3
+FC_KERNEL_FORWARD, FC_KERNEL_BACKWARD, FC_KERNEL_QUERY_BACKWARD, FC_KERNEL_GATHER_PROBE, FC_KERNEL_FACES = range(5)
 
 # the in-tree build; FC_LIB_PATH selects another build of the same sources
 LIB_PATH = os.environ.get("FC_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -36,7 +36,8 @@ class fc_grid(C.Structure):
 
 
 class fc_mesh(C.Structure):
-    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("n_verts", C.c_int32)]
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("n_verts", C.c_int32),
+                ("tris", C.c_void_p), ("n_tris", C.c_int32)]
 
 
 class fc_batch_desc(C.Structure):
@@ -47,7 +48,11 @@ class fc_batch_desc(C.Structure):
 
 
 class fc_candidates(C.Structure):
-    _fields_ = [("phi", C.c_void_p), ("normal", C.c_void_p), ("bin", C.c_void_p)]
+    _fields_ = [("phi", C.c_void_p), ("normal", C.c_void_p), ("bin", C.c_void_p), ("point", C.c_void_p)]
+
+
+class fc_pgd(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("step0", C.c_float)]
 
 
 class fc_contacts(C.Structure):
@@ -94,6 +99,9 @@ SIGNATURES = {
     "fc_batch_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "fc_batch_read_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32]),
     "fc_gather_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fc_sdf_query_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_pgd), C.POINTER(fc_candidates),
+                                     C.POINTER(fc_contacts), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fc_batch_face_queries": (C.c_int64, [C.c_void_p]),
     "fc_status_str": (C.c_char_p, [C.c_int]),
     "fc_last_hip_error": (C.c_int32, []),
     "fc_version": (C.c_char_p, []),
@@ -187,16 +195,24 @@ class Batch:
             self.grid_tensors.append(t)
         mdesc = (fc_mesh * len(meshes))()
         self.mesh_tensors = []
+        self.tri_tensors = []
         for i, m in enumerate(meshes):
             v = np.ascontiguousarray(np.asarray(m.verts, dtype=np.float32).T)  # (3, n)
             t = torch.from_numpy(v).to(self.device)
             n = v.shape[1]
+            tris = getattr(m, "tris", None)
+            tt, nt = None, 0
+            if tris is not None and len(tris):
+                tt = torch.from_numpy(np.ascontiguousarray(np.asarray(tris, dtype=np.int32).T)).to(self.device)
+                nt = int(tt.shape[1])  # (3, n_tris): corner a of every face, then b, then c
             if n:
                 mdesc[i] = fc_mesh(C.c_void_p(t[0].data_ptr()), C.c_void_p(t[1].data_ptr()),
-                                   C.c_void_p(t[2].data_ptr()), n)
+                                   C.c_void_p(t[2].data_ptr()), n, None if tt is None else C.c_void_p(tt.data_ptr()),
+                                   nt)
             else:
-                mdesc[i] = fc_mesh(None, None, None, 0)
+                mdesc[i] = fc_mesh(None, None, None, 0, None, 0)
             self.mesh_tensors.append(t)
+            self.tri_tensors.append(tt)
         self.mesh_sizes = [int(m.verts.shape[0]) for m in meshes]
         eg = np.ascontiguousarray(env_grid, dtype=np.int32)
         em = np.ascontiguousarray(env_mesh, dtype=np.int32)
@@ -211,6 +227,7 @@ class Batch:
         _check(L.fc_batch_create(C.byref(desc), C.byref(h)), "fc_batch_create")
         self.handle = h
         self.Q = int(L.fc_batch_queries(h))
+        self.Qf = int(L.fc_batch_face_queries(h))
         self.ws_bytes = int(L.fc_workspace_bytes(h))
         self.workspace = torch.zeros(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
         if self.workspace.data_ptr() % 256:
@@ -234,6 +251,16 @@ class Batch:
         return dict(phi=torch.empty(self.Q, dtype=torch.float32, device=self.device),
                     normal=torch.empty(3, self.Q, dtype=torch.float32, device=self.device),
                     bin=torch.empty(self.Q, dtype=torch.int16, device=self.device))
+
+    def new_face_candidates(self):
+        """Per-face candidates: phi, normal [3][Qf], bin, point [3][Qf]."""
+        import torch
+
+        Q = max(self.Qf, 1)
+        return dict(phi=torch.empty(Q, dtype=torch.float32, device=self.device),
+                    normal=torch.empty(3, Q, dtype=torch.float32, device=self.device),
+                    bin=torch.empty(Q, dtype=torch.int16, device=self.device),
+                    point=torch.empty(3, Q, dtype=torch.float32, device=self.device))
 
     def new_contacts(self):
         import torch
@@ -290,7 +317,8 @@ class Batch:
 
 
 def _cand_struct(c):
-    return None if c is None else fc_candidates(_ptr(c["phi"]), _ptr(c["normal"]), _ptr(c["bin"]))
+    return None if c is None else fc_candidates(_ptr(c["phi"]), _ptr(c["normal"]), _ptr(c["bin"]),
+                                                _ptr(c.get("point")))
 
 
 def _contacts_struct(o):
@@ -331,6 +359,18 @@ def fc_sdf_query_and_backward(batch: Batch, pose, fused_out, k, grads, upstream=
                                            _ptr(upstream), C.byref(_grads_struct(grads)),
                                            C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes,
                                            _stream(stream)), "fc_sdf_query_and_backward")
+
+
+PGD_ITERS, PGD_STEP0 = 8, 0.5  # per-face descent defaults (trials, first step in face sizes)
+
+
+def fc_sdf_query_faces(batch: Batch, pose, cand=None, fused_out=None, iters=PGD_ITERS, step0=PGD_STEP0,
+                       stream=None):
+    cs, os_ = _cand_struct(cand), _contacts_struct(fused_out)
+    p = fc_pgd(int(iters), float(step0))
+    _check(lib().fc_sdf_query_faces(batch.handle, _ptr(pose), C.byref(p), _byref(cs), _byref(os_),
+                                    C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes, _stream(stream)),
+           "fc_sdf_query_faces")
 
 
 def fc_gather_probe(batch: Batch, pose, sink, stream=None):

@@ -53,14 +53,14 @@ FAKE = 0x100000  # never dereferenced: validation only reads host arrays
 
 
 def make_desc(n_env=2, K=16, dims=(4, 4, 4), h=0.1, dtype=0, n_verts=5, env_grid=None, mesh_null=False,
-              second_grid_dtype=None):
+              second_grid_dtype=None, n_tris=0, tris_null=False):
     grids = (fc.fc_grid * 2)()
     grids[0] = fc.fc_grid(C.c_void_p(FAKE), dtype, 0, *dims, (C.c_float * 3)(0, 0, 0), h)
     grids[1] = fc.fc_grid(C.c_void_p(FAKE), dtype if second_grid_dtype is None else second_grid_dtype, 0, *dims,
                           (C.c_float * 3)(0, 0, 0), h)
     meshes = (fc.fc_mesh * 1)()
     p = None if mesh_null else C.c_void_p(FAKE)
-    meshes[0] = fc.fc_mesh(p, p, p, n_verts)
+    meshes[0] = fc.fc_mesh(p, p, p, n_verts, None if tris_null else C.c_void_p(FAKE), n_tris)
     eg = np.zeros(n_env, np.int32) if env_grid is None else np.asarray(env_grid, np.int32)
     em = np.zeros(n_env, np.int32)
     dirs = np.zeros((3, max(K, 1)), np.float32)
@@ -86,6 +86,8 @@ def make_desc(n_env=2, K=16, dims=(4, 4, 4), h=0.1, dtype=0, n_verts=5, env_grid
     (dict(env_grid=[-1, 0]), fc.FC_ERR_SHAPE),
     (dict(n_verts=-1), fc.FC_ERR_SHAPE),
     (dict(mesh_null=True), fc.FC_ERR_NULL),
+    (dict(n_tris=-1), fc.FC_ERR_SHAPE),
+    (dict(n_tris=4, tris_null=True), fc.FC_ERR_NULL),
 ])
 def test_batch_create_rejects(L, kw, status):
     desc = make_desc(**kw)
@@ -104,6 +106,8 @@ def test_null_arguments(L):
     assert L.fc_sdf_query_and_backward(None, None, None, 1.0, None, None, None, 0, None) == fc.FC_ERR_NULL
     assert L.fc_graph_launch(None, None) == fc.FC_ERR_NULL
     assert L.fc_gather_probe(None, None, None, None) == fc.FC_ERR_NULL
+    assert L.fc_sdf_query_faces(None, None, None, None, None, None, 0, None) == fc.FC_ERR_NULL
+    assert L.fc_batch_face_queries(None) == -1
     assert L.fc_batch_set_timing(None, 4) == fc.FC_ERR_NULL
     assert L.fc_batch_read_timing(None, None, None, 0) == -1
     assert L.fc_batch_queries(None) == -1

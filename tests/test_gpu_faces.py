@@ -1,0 +1,170 @@
+"""GPU parity of per-face contact generation (fc_sdf_query_faces: projected
+gradient descent of the SDF over each face) against the FP64 oracle, through
+the C ABI.
+
+The descent's accept/reject decisions compare phi values, so an FP32 run and
+an FP64 run may part ways where two values are within rounding of each other;
+both paths are then valid descents.  So the checks are:
+  * for every face, what is unique given the GPU's own result: its phi is the
+    FP64 field at its point (within the FP32 sampling tolerance), the point
+    lies on the face, phi never exceeds the field at the face's centroid,
+    the normal is the FP64 gradient direction there, the bin is the FP32 rule
+    on the GPU's normal, and the reduction is exact on the GPU's candidates;
+  * against the oracle's own descent: the final phi agrees within the FP32
+    tolerance for at least 99 % of the faces."""
+import numpy as np
+import pytest
+
+from _gpu_common import assert_same, bins_fp32, to_np, torch_gpu
+from oracle import faces as OF
+from oracle import query as OQ
+from oracle import reduce as ORD
+from paper_2205_03532_amd import fc
+from paper_2205_03532_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+ITERS, STEP0 = fc.PGD_ITERS, fc.PGD_STEP0
+PHI_TOL = 1e-6  # m: FP32 sampling and descent rounding, as for vertex queries
+AGREE = 0.99  # fraction of faces whose final phi matches the FP64 descent
+
+
+def face_offsets(w):
+    """Per-env first face query (faces of env e at off[e] .. off[e + 1])."""
+    nt = [0 if m.tris is None else len(m.tris) for m in w.meshes]
+    return np.concatenate([[0], np.cumsum([nt[int(m)] for m in w.env_mesh])])
+
+
+def run_faces(b, pose, iters=ITERS, cand=True, fused=True):
+    torch = torch_gpu()
+    c = b.new_face_candidates() if cand else None
+    o = b.new_contacts() if fused else None
+    fc.fc_sdf_query_faces(b, pose, cand=c, fused_out=o, iters=iters, step0=STEP0)
+    torch.cuda.synchronize()
+    return (to_np(c) if cand else None), (to_np(o) if fused else None)
+
+
+def check_faces(w, c, o, envs, iters=ITERS):
+    off = face_offsets(w)
+    r = OF.query_faces_workload(w, iters, STEP0, envs)
+    rows = np.concatenate([np.arange(off[e], off[e + 1]) for e in envs])
+    gp = c["phi"][rows].astype(np.float64)
+    gx = c["point"][:, rows].T.astype(np.float64)
+    g_in = np.isfinite(gp)
+    # the GPU's phi is the field at its point
+    grid_of = {e: w.grids[int(w.env_grid[e])] for e in envs}
+    g0 = grid_of[envs[0]]
+    assert all(grid_of[e] is g0 for e in envs), "one grid per checked set"
+    vals = OQ.grid_values_f64(g0.values, g0.dtype)
+    phi_at, grad_at, ins_at, _ = OQ.sample(vals, g0.origin, g0.h, g0.dims, gx)
+    assert np.all(ins_at[g_in]), "a GPU point marked inside lies outside the grid"
+    err = np.abs(gp[g_in] - phi_at[g_in])
+    assert err.max() <= PHI_TOL, err.max()
+    # the point lies on its face (barycentric coordinates from the FP64 corners)
+    X = r["corners"]
+    e1, e2 = X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]
+    G = np.stack([e1, e2], -1)  # (F, 3, 2)
+    A = np.einsum("fki,fkj->fij", G, G)
+    rhs = np.einsum("fki,fk->fi", G, gx - X[:, 0])
+    ok_det = np.abs(np.linalg.det(A)) > 1e-30
+    bc = np.zeros((len(X), 2))
+    bc[ok_det] = np.linalg.solve(A[ok_det], rhs[ok_det][..., None])[..., 0]
+    on = g_in & ok_det
+    assert np.all(bc[on] >= -1e-4) and np.all(bc[on].sum(1) <= 1 + 1e-4)
+    resid = np.linalg.norm(np.einsum("fij,fj->fi", G, bc) - (gx - X[:, 0]), axis=1)
+    scale = np.sqrt(np.sum(e1 * e1, 1) + np.sum(e2 * e2, 1))
+    assert np.all(resid[on] <= 1e-5 * scale[on] + 1e-9)
+    # never above the start
+    assert np.all(gp[g_in] <= r["phi0"][g_in] + PHI_TOL)
+    # agreement with the FP64 descent
+    both = g_in & np.isfinite(r["phi"])
+    agree = np.abs(gp[both] - r["phi"][both]) <= PHI_TOL
+    frac = agree.mean() if both.any() else 1.0
+    assert frac >= AGREE, frac
+    assert (g_in != np.isfinite(r["phi"])).mean() <= 1 - AGREE
+    # candidates, normals, bins
+    cand = g_in & (gp < np.float32(w.margin))
+    b = c["bin"][rows].astype(np.int64)
+    assert np.array_equal(b >= 0, cand)
+    gn = c["normal"][:, rows].T.astype(np.float64)
+    gnorm = np.linalg.norm(grad_at, axis=1)
+    ref_n = grad_at / np.where(gnorm > 0, gnorm, 1)[:, None]
+    nerr = np.linalg.norm(gn[cand] - ref_n[cand], axis=1)
+    assert np.mean(nerr <= 1e-5) >= AGREE, np.mean(nerr <= 1e-5)
+    sel = np.nonzero(cand)[0]
+    assert np.array_equal(bins_fp32(c["normal"][:, rows[sel]], w.bins), b[sel])
+    # exact reduction of the GPU's own candidates; winners' records are the candidates'
+    env = np.concatenate([np.full(off[e + 1] - off[e], e) for e in envs])
+    fidx = rows - off[env]
+    depth = (-gp).astype(np.float32)
+    wv, wd, _ = ORD.reduce_contacts(env, fidx, depth, b, cand, w.n_env, w.K)
+    K = w.K
+    for e in envs:
+        s = slice(e * K, (e + 1) * K)
+        assert np.array_equal(o["vidx"][s], wv[e]), e
+        assert np.array_equal(o["depth"][s].view(np.uint32), wd[e].view(np.uint32)), e
+        full = wv[e] >= 0
+        q = off[e] + wv[e][full]
+        assert np.array_equal(o["point"][:, s][:, full].view(np.uint32), c["point"][:, q].view(np.uint32)), e
+        assert np.array_equal(o["normal"][:, s][:, full].view(np.uint32), c["normal"][:, q].view(np.uint32)), e
+        assert o["count"][e] == int(full.sum())
+    return dict(faces=int(len(rows)), inside=int(g_in.sum()), cand=int(cand.sum()), agree=float(frac))
+
+
+def test_torus_faces_match_oracle():
+    torch_gpu()
+    w = W.subset(W.torus_workload(), range(48))
+    b = fc.Batch.from_workload(w)
+    c, o = run_faces(b, fc.pose_tensor(w.pose))
+    st = check_faces(w, c, o, list(range(w.n_env)))
+    print("torus faces:", st)
+    assert st["cand"] > 1000
+
+
+@pytest.mark.parametrize("layout", ["linear", "brick"])
+def test_nutbolt_faces_match_oracle(layout):
+    torch_gpu()
+    w = W.subset(W.nut_bolt_workload(), range(0, 1000, 125))
+    b = fc.Batch.from_workload(w, layout=layout)
+    c, o = run_faces(b, fc.pose_tensor(w.pose))
+    st = check_faces(w, c, o, list(range(w.n_env)))
+    print("nut-bolt faces:", layout, st)
+    assert st["cand"] > 1000
+
+
+def test_zero_iterations_is_the_centroid_and_calls_repeat():
+    torch_gpu()
+    w = W.subset(W.torus_workload(), range(8))
+    b = fc.Batch.from_workload(w)
+    pose = fc.pose_tensor(w.pose)
+    c, o = run_faces(b, pose, iters=0)
+    check_faces(w, c, o, list(range(w.n_env)), iters=0)
+    c1, o1 = run_faces(b, pose)
+    c2, o2 = run_faces(b, pose)
+    _, o3 = run_faces(b, pose, cand=False)
+    assert_same(c1, c2)
+    assert_same(o1, o2)
+    assert_same(o1, o3)
+
+
+def test_meshes_without_faces_give_empty_lists():
+    """A mixed batch whose peg meshes carry no triangles: those envs get empty
+    face contact lists; the nut envs get theirs."""
+    torch_gpu()
+    w = W.subset(W.mixed_workload(), range(0, 4096, 64))
+    b = fc.Batch.from_workload(w)
+    c, o = run_faces(b, fc.pose_tensor(w.pose))
+    has = np.array([w.meshes[int(m)].tris is not None for m in w.env_mesh])
+    assert np.all(o["count"][~has] == 0) and np.all(o["vidx"].reshape(w.n_env, w.K)[~has] == -1)
+    assert o["count"][has].sum() > 0
+    assert b.Qf == int(face_offsets(w)[-1])
+
+
+def test_face_kernel_timing_id():
+    torch_gpu()
+    w = W.subset(W.torus_workload(), range(4))
+    b = fc.Batch.from_workload(w)
+    b.set_timing(1)
+    run_faces(b, fc.pose_tensor(w.pose))
+    ms, kid = b.read_timing()
+    b.set_timing(0)
+    assert list(kid) == [fc.FC_KERNEL_FACES] and ms[0] > 0
