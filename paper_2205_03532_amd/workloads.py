@@ -413,8 +413,9 @@ def rect_peg(half_x, half_y, length, n_per_side) -> Mesh:
 
 
 def tetrahedron_mesh(scale=1.0):
+    """Regular tetrahedron, 4 vertices, 4 outward-wound triangles."""
     v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64) * scale
-    t = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], dtype=np.int32)
+    t = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]], dtype=np.int32)
     return v, t
 
 
