@@ -323,6 +323,56 @@ size_t fc_grid_brick_bytes(const fc_grid* src, int32_t layout);
 fc_status fc_grid_to_bricks(const fc_grid* src, int32_t layout, void* dst_data, size_t dst_bytes, fc_grid* dst,
                             void* stream);
 
+/* ---- mesh -> SDF bake -------------------------------------------------- */
+
+/* Section III-A: body B's SDF is generated from its triangle mesh ahead of
+ * time by sampling it on the grid.  Here every node gets the Euclidean
+ * distance to the nearest triangle (closest point by Ericson's
+ * Voronoi-region tests), negative inside.  The sign is that of (p - q) . n
+ * for the closest point q and the angle-weighted pseudonormal n of the
+ * feature q lies on (Baerentzen and Aanaes 2005: the face normal, for an edge
+ * the sum of its two faces' normals, for a vertex the angle-weighted sum of
+ * its faces' normals), which is exact for a closed mesh.  Among triangles at
+ * exactly the same distance the lowest index wins.
+ *
+ * Two steps: fc_bake_table (host, FP64) turns the mesh into a table of per-
+ * triangle corners and pseudonormals, which the caller copies to the device;
+ * fc_bake_sdf (asynchronous) evaluates every node against it. */
+
+/* Bytes of the table for n_tris triangles: (10 n_tris + 2 ceil(n_tris / 32))
+ * float4 records of 16 bytes; 0 if n_tris < 4 or n_tris > 2^24. */
+size_t fc_bake_table_bytes(int32_t n_tris);
+
+/* Fill `table` (host, 16-byte aligned, fc_bake_table_bytes bytes) from a mesh:
+ * verts host [n_verts][3] (metres), tris host [n_tris][3] vertex indices.
+ * The mesh must be closed and consistently wound with outward normals by the
+ * right-hand rule: every directed edge occurs once and its reverse once
+ * (else FC_ERR_SHAPE, also for an index outside [0, n_verts) or a face with a
+ * repeated index), every face has non-zero area and the enclosed volume is
+ * positive (else FC_ERR_RANGE, also for a non-finite vertex).  n_verts >= 4,
+ * 4 <= n_tris <= 2^24 (else FC_ERR_SHAPE); a short table: FC_ERR_WORKSPACE.
+ * Layout, triangles in the order of a Morton curve over their centroids:
+ *   [n_tris][3] float4  corner a (w: the mesh's triangle index, int32 bits),
+ *                       b - a, c - a (w = 0);
+ *   [n_tris][7] float4  pseudonormals: face, edge ab, edge ac, edge bc,
+ *                       vertex a, vertex b, vertex c (w = 0);
+ *   [ceil(n_tris/32)][2] float4  per run of 32 consecutive triangles the
+ *                       bounding box of their corners (lo, hi; w = 0, except
+ *                       the first box's lo.w: the largest absolute vertex
+ *                       coordinate).
+ * Host only; no HIP call. */
+fc_status fc_bake_table(const float* verts, int32_t n_verts, const int32_t* tris, int32_t n_tris, void* table,
+                        size_t table_bytes);
+
+/* Bake: out (device, [nz][ny][nx] FP32, node (i,j,k) at origin + h*(i,j,k))
+ * = the signed distance of the mesh whose table (device, 16-byte aligned,
+ * from fc_bake_table) has n_tris triangles.  nx, ny, nz >= 1 with
+ * nx*ny*nz < 2^31, 4 <= n_tris <= 2^24 (else FC_ERR_SHAPE); h > 0 and all of
+ * origin (host [3]) finite (else FC_ERR_RANGE).  The result can be passed as
+ * the data of a linear FC_F32 fc_grid with the same nx, ny, nz, origin, h. */
+fc_status fc_bake_sdf(const void* table, int32_t n_tris, int32_t nx, int32_t ny, int32_t nz, const float* origin,
+                      float h, float* out, void* stream);
+
 /* ---- autotuning and diagnostics ----------------------------------------- */
 
 /* Load a launch-shape cache written by the autotuner: a JSON object

@@ -26,40 +26,45 @@ import numpy as np
 FACE, EDGE_AB, EDGE_AC, EDGE_BC, VERT_A, VERT_B, VERT_C = range(7)
 
 
+def _dot(x, y):
+    return np.sum(x * y, axis=-1)
+
+
 def closest_on_triangle(P, a, b, c):
-    """Closest point of triangle (a, b, c) to each row of P (n, 3) and the
-    feature it lies on (FACE, EDGE_*, VERT_*), by Ericson's region tests."""
+    """Closest point of triangle (a, b, c) to P and the feature it lies on
+    (FACE, EDGE_*, VERT_*), by Ericson's region tests.  P, a, b, c broadcast
+    against each other over leading axes (last axis = 3); returns the point
+    (..., 3) and the feature code (...)."""
+    P, a, b, c = (np.asarray(x, dtype=np.float64) for x in (P, a, b, c))
+    shape = np.broadcast_shapes(P.shape, a.shape, b.shape, c.shape)
+    P, a, b, c = (np.broadcast_to(x, shape) for x in (P, a, b, c))
     ab, ac = b - a, c - a
     ap = P - a
-    d1, d2 = ap @ ab, ap @ ac
+    d1, d2 = _dot(ap, ab), _dot(ap, ac)
     bp = P - b
-    d3, d4 = bp @ ab, bp @ ac
+    d3, d4 = _dot(bp, ab), _dot(bp, ac)
     cp = P - c
-    d5, d6 = cp @ ab, cp @ ac
+    d5, d6 = _dot(cp, ab), _dot(cp, ac)
     vc = d1 * d4 - d3 * d2
     vb = d5 * d2 - d1 * d6
     va = d3 * d6 - d5 * d4
-    n = len(P)
-    q = np.empty((n, 3))
-    feat = np.full(n, -1, dtype=np.int64)
-    done = np.zeros(n, dtype=bool)
-
-    def take(mask, pts, code):
-        m = mask & ~done
-        q[m] = pts[m] if pts.ndim == 2 else pts
-        feat[m] = code
-        done[m] = True
-
     with np.errstate(divide="ignore", invalid="ignore"):
-        take((d1 <= 0) & (d2 <= 0), a, VERT_A)
-        take((d3 >= 0) & (d4 <= d3), b, VERT_B)
-        take((vc <= 0) & (d1 >= 0) & (d3 <= 0), a + (d1 / (d1 - d3))[:, None] * ab, EDGE_AB)
-        take((d6 >= 0) & (d5 <= d6), c, VERT_C)
-        take((vb <= 0) & (d2 >= 0) & (d6 <= 0), a + (d2 / (d2 - d6))[:, None] * ac, EDGE_AC)
+        # the regions in Ericson's order: the first test that holds names the feature
+        feat = np.select([(d1 <= 0) & (d2 <= 0),
+                          (d3 >= 0) & (d4 <= d3),
+                          (vc <= 0) & (d1 >= 0) & (d3 <= 0),
+                          (d6 >= 0) & (d5 <= d6),
+                          (vb <= 0) & (d2 >= 0) & (d6 <= 0),
+                          (va <= 0) & ((d4 - d3) >= 0) & ((d5 - d6) >= 0)],
+                         [VERT_A, VERT_B, EDGE_AB, VERT_C, EDGE_AC, EDGE_BC], FACE)
+        # q = a + u ab + v ac; on edge bc, b + w (c - b) = a + (1 - w) ab + w ac
         w = (d4 - d3) / ((d4 - d3) + (d5 - d6))
-        take((va <= 0) & ((d4 - d3) >= 0) & ((d5 - d6) >= 0), b + w[:, None] * (c - b), EDGE_BC)
         den = 1.0 / (va + vb + vc)
-        take(np.ones(n, dtype=bool), a + (vb * den)[:, None] * ab + (vc * den)[:, None] * ac, FACE)
+        u = np.select([feat == VERT_B, feat == EDGE_AB, feat == EDGE_BC, feat == FACE],
+                      [1.0, d1 / (d1 - d3), 1.0 - w, vb * den], 0.0)
+        v = np.select([feat == VERT_C, feat == EDGE_AC, feat == EDGE_BC, feat == FACE],
+                      [1.0, d2 / (d2 - d6), w, vc * den], 0.0)
+    q = a + u[..., None] * ab + v[..., None] * ac
     return q, feat
 
 
@@ -87,31 +92,50 @@ def pseudonormals(V, T):
     return fn, en, vn
 
 
-def bake(V, T, dims, origin, h):
-    """Signed distance at every node of the grid, [nz][ny][nx] float64."""
+def feature_normals(V, T):
+    """(m, 7, 3): for every triangle the pseudonormal of each of its features,
+    indexed by the feature codes."""
+    T = np.asarray(T, dtype=np.int64)
+    fn, en, vn = pseudonormals(V, T)
+    N = np.empty((len(T), 7, 3))
+    N[:, FACE] = fn
+    N[:, EDGE_AB], N[:, EDGE_AC], N[:, EDGE_BC] = en[:, 0], en[:, 1], en[:, 2]
+    N[:, VERT_A], N[:, VERT_B], N[:, VERT_C] = vn[T[:, 0]], vn[T[:, 1]], vn[T[:, 2]]
+    return N
+
+
+def bake_points(V, T, P, pair_budget=1 << 20):
+    """Signed distance of the mesh at each row of P (n, 3), float64: the
+    distance to the nearest triangle (the lowest index among exact ties),
+    negative where (P - q) . n < 0 for the closest point q and the
+    pseudonormal n of its feature."""
     V = np.asarray(V, dtype=np.float64)
     T = np.asarray(T, dtype=np.int64)
+    P = np.asarray(P, dtype=np.float64).reshape(-1, 3)
+    A, B, C = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    N = feature_normals(V, T)
+    out = np.empty(len(P))
+    step = max(1, pair_budget // max(1, len(T)))
+    for s in range(0, len(P), step):
+        p = P[s:s + step]
+        q, feat = closest_on_triangle(p[:, None, :], A[None], B[None], C[None])
+        d = np.sqrt(np.sum((p[:, None, :] - q) ** 2, axis=-1))
+        j = np.argmin(d, axis=1)  # the first (lowest) index among exact ties
+        r = np.arange(len(p))
+        n = N[j, feat[r, j]]
+        sign = np.where(np.sum((p - q[r, j]) * n, axis=1) < 0.0, -1.0, 1.0)
+        out[s:s + step] = sign * d[r, j]
+    return out
+
+
+def grid_nodes(dims, origin, h):
+    """Node positions (nz, ny, nx, 3): node (i, j, k) at origin + h (i, j, k)."""
     nx, ny, nz = dims
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    P = np.stack([origin[0] + h * x, origin[1] + h * y, origin[2] + h * z], -1).reshape(-1, 3)
-    fn, en, vn = pseudonormals(V, T)
-    best = np.full(len(P), np.inf)
-    nrm = np.zeros((len(P), 3))
-    qbest = np.zeros((len(P), 3))
-    for f, (i, j, k) in enumerate(T):
-        q, feat = closest_on_triangle(P, V[i], V[j], V[k])
-        d = np.sqrt(np.sum((P - q) ** 2, axis=1))
-        closer = d < best  # strict: the lowest index keeps exact ties
-        if not closer.any():
-            continue
-        n = np.empty((len(P), 3))
-        n[feat == FACE] = fn[f]
-        for code, slot in ((EDGE_AB, 0), (EDGE_AC, 1), (EDGE_BC, 2)):
-            n[feat == code] = en[f, slot]
-        for code, vi in ((VERT_A, i), (VERT_B, j), (VERT_C, k)):
-            n[feat == code] = vn[vi]
-        best = np.where(closer, d, best)
-        nrm = np.where(closer[:, None], n, nrm)
-        qbest = np.where(closer[:, None], q, qbest)
-    sign = np.where(np.sum((P - qbest) * nrm, axis=1) < 0.0, -1.0, 1.0)
-    return (sign * best).reshape(nz, ny, nx)
+    return np.stack([origin[0] + h * x, origin[1] + h * y, origin[2] + h * z], -1)
+
+
+def bake(V, T, dims, origin, h):
+    """Signed distance at every node of the grid, [nz][ny][nx] float64."""
+    nx, ny, nz = dims
+    return bake_points(V, T, grid_nodes(dims, origin, h).reshape(-1, 3)).reshape(nz, ny, nx)

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -771,6 +772,140 @@ fc_status validate_backward(const fc_batch* b, const float* pose, float k, const
   return check_ws(b, ws, ws_bytes);
 }
 
+// ---- mesh -> SDF bake -------------------------------------------------------
+
+constexpr long long kBakeMaxTris = 1LL << 24;
+constexpr int kBakeRecord = 3 + kBakeFeatures;  // float4 per triangle: a, ab, ac, 7 pseudonormals
+
+long long bake_clusters(long long n_tris) { return (n_tris + kBakeCluster - 1) / kBakeCluster; }
+
+struct D3 {
+  double x, y, z;
+};
+D3 sub(const D3& a, const D3& b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+D3 add(const D3& a, const D3& b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+D3 scale(const D3& a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+double dot(const D3& a, const D3& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+D3 cross(const D3& a, const D3& b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+double norm(const D3& a) { return std::sqrt(dot(a, a)); }
+
+// interior angle at p of the triangle (p, q, r)
+double corner_angle(const D3& p, const D3& q, const D3& r) {
+  const D3 u = sub(q, p), v = sub(r, p);
+  const double c = dot(u, v) / (norm(u) * norm(v));
+  return std::acos(std::max(-1.0, std::min(1.0, c)));
+}
+
+// Pseudonormal table of a closed, consistently outward-wound mesh (face
+// normal; per edge the sum of its two faces' unit normals; per vertex the
+// angle-weighted sum of its faces' unit normals), computed in FP64.
+fc_status build_bake_table(const float* verts, int n_verts, const int32_t* tris, int n_tris, float4* out) {
+  std::vector<D3> V(n_verts);
+  for (int i = 0; i < n_verts; ++i) {
+    V[i] = {verts[3 * i], verts[3 * i + 1], verts[3 * i + 2]};
+    if (!std::isfinite(V[i].x) || !std::isfinite(V[i].y) || !std::isfinite(V[i].z)) return FC_ERR_RANGE;
+  }
+  for (long long k = 0; k < 3LL * n_tris; ++k)
+    if (tris[k] < 0 || tris[k] >= n_verts) return FC_ERR_SHAPE;
+  // closed and consistently wound: every directed edge once, and its reverse once
+  std::vector<std::pair<uint64_t, int>> edges;  // (p << 32 | q, face)
+  edges.reserve(3 * (size_t)n_tris);
+  for (int f = 0; f < n_tris; ++f) {
+    const int32_t* t = tris + 3 * f;
+    if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2]) return FC_ERR_SHAPE;
+    for (int e = 0; e < 3; ++e)
+      edges.push_back({((uint64_t)(uint32_t)t[e] << 32) | (uint32_t)t[(e + 1) % 3], f});
+  }
+  std::sort(edges.begin(), edges.end());
+  for (size_t i = 1; i < edges.size(); ++i)
+    if (edges[i].first == edges[i - 1].first) return FC_ERR_SHAPE;
+  auto twin = [&](uint32_t p, uint32_t q) -> int {  // face owning the directed edge (p, q), -1 if none
+    const uint64_t key = ((uint64_t)p << 32) | q;
+    auto it = std::lower_bound(edges.begin(), edges.end(), std::make_pair(key, -1));
+    return (it != edges.end() && it->first == key) ? it->second : -1;
+  };
+  std::vector<D3> fn(n_tris);
+  double vol6 = 0.0;
+  for (int f = 0; f < n_tris; ++f) {
+    const int32_t* t = tris + 3 * f;
+    const D3 n = cross(sub(V[t[1]], V[t[0]]), sub(V[t[2]], V[t[0]]));
+    const double len = norm(n);
+    if (!(len > 0.0)) return FC_ERR_RANGE;  // zero-area face: no normal
+    fn[f] = scale(n, 1.0 / len);
+    vol6 += dot(V[t[0]], cross(V[t[1]], V[t[2]]));
+  }
+  for (int f = 0; f < n_tris; ++f) {
+    const int32_t* t = tris + 3 * f;
+    for (int e = 0; e < 3; ++e)
+      if (twin((uint32_t)t[(e + 1) % 3], (uint32_t)t[e]) < 0) return FC_ERR_SHAPE;  // open edge
+  }
+  if (!(vol6 > 0.0)) return FC_ERR_RANGE;  // wound inward (or no volume)
+  std::vector<D3> vn(n_verts, D3{0.0, 0.0, 0.0});
+  for (int f = 0; f < n_tris; ++f) {
+    const int32_t* t = tris + 3 * f;
+    for (int e = 0; e < 3; ++e) {
+      const int p = t[e], q = t[(e + 1) % 3], r = t[(e + 2) % 3];
+      vn[p] = add(vn[p], scale(fn[f], corner_angle(V[p], V[q], V[r])));
+    }
+  }
+  // spatial order: Morton code of the centroid over the mesh's bounding box
+  D3 lo = V[0], hi = V[0];
+  for (const D3& v : V) {
+    lo = {std::min(lo.x, v.x), std::min(lo.y, v.y), std::min(lo.z, v.z)};
+    hi = {std::max(hi.x, v.x), std::max(hi.y, v.y), std::max(hi.z, v.z)};
+  }
+  const double span = std::max({hi.x - lo.x, hi.y - lo.y, hi.z - lo.z, 1e-300});
+  std::vector<std::pair<uint32_t, int>> order(n_tris);
+  for (int f = 0; f < n_tris; ++f) {
+    const int32_t* t = tris + 3 * f;
+    const D3 c = scale(add(add(V[t[0]], V[t[1]]), V[t[2]]), 1.0 / 3.0);
+    const double q[3] = {(c.x - lo.x) / span, (c.y - lo.y) / span, (c.z - lo.z) / span};
+    uint32_t code = 0;
+    for (int a = 0; a < 3; ++a) {
+      const uint32_t u = (uint32_t)std::min(1023.0, std::max(0.0, q[a] * 1024.0));
+      for (int bit = 0; bit < 10; ++bit) code |= ((u >> bit) & 1u) << (3 * bit + a);
+    }
+    order[f] = {code, f};
+  }
+  std::sort(order.begin(), order.end());
+  auto put = [](float4* o, const D3& d) { *o = make_float4((float)d.x, (float)d.y, (float)d.z, 0.f); };
+  const long long nc = bake_clusters(n_tris);
+  float4* box = out + (size_t)kBakeRecord * n_tris;
+  for (long long c = 0; c < nc; ++c) {
+    box[2 * c] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+    box[2 * c + 1] = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+  }
+  for (int s = 0; s < n_tris; ++s) {
+    const int f = order[s].second;
+    const int32_t* t = tris + 3 * f;
+    const int a = t[0], b = t[1], c = t[2];
+    float4* pos = out + 3 * (size_t)s;
+    float4* nrm = out + 3 * (size_t)n_tris + (size_t)kBakeFeatures * s;
+    float4* bl = box + 2 * (s / kBakeCluster);
+    for (int k = 0; k < 3; ++k) {  // the box of the corners as given (FP32)
+      const float* v = verts + 3 * t[k];
+      bl[0] = make_float4(std::min(bl[0].x, v[0]), std::min(bl[0].y, v[1]), std::min(bl[0].z, v[2]), 0.f);
+      bl[1] = make_float4(std::max(bl[1].x, v[0]), std::max(bl[1].y, v[1]), std::max(bl[1].z, v[2]), 0.f);
+    }
+    put(pos, V[a]);
+    int32_t fi = f;
+    std::memcpy(&pos->w, &fi, sizeof(fi));  // the mesh's index, for ties
+    put(pos + 1, sub(V[b], V[a]));
+    put(pos + 2, sub(V[c], V[a]));
+    put(nrm + kBakeFace, fn[f]);
+    put(nrm + kBakeEdgeAB, add(fn[f], fn[twin((uint32_t)b, (uint32_t)a)]));
+    put(nrm + kBakeEdgeAC, add(fn[f], fn[twin((uint32_t)a, (uint32_t)c)]));
+    put(nrm + kBakeEdgeBC, add(fn[f], fn[twin((uint32_t)c, (uint32_t)b)]));
+    put(nrm + kBakeVertA, vn[a]);
+    put(nrm + kBakeVertB, vn[b]);
+    put(nrm + kBakeVertC, vn[c]);
+  }
+  double vmax = 0.0;  // the mesh's largest coordinate, which scales the cull slack
+  for (const D3& v : V) vmax = std::max({vmax, std::fabs(v.x), std::fabs(v.y), std::fabs(v.z)});
+  box[0].w = (float)vmax;
+  return FC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1093,6 +1228,58 @@ fc_status fc_grid_to_bricks(const fc_grid* src, int32_t layout, void* dst_data, 
   *dst = *src;
   dst->data = dst_data;
   dst->layout = layout;
+  return FC_OK;
+}
+
+size_t fc_bake_table_bytes(int32_t n_tris) {
+  if (n_tris < 4 || n_tris > kBakeMaxTris) return 0;
+  return ((size_t)n_tris * kBakeRecord + 2 * (size_t)bake_clusters(n_tris)) * sizeof(float4);
+}
+
+fc_status fc_bake_table(const float* verts, int32_t n_verts, const int32_t* tris, int32_t n_tris, void* table,
+                        size_t table_bytes) {
+  if (!verts || !tris || !table) return FC_ERR_NULL;
+  if (n_verts < 4 || n_tris < 4 || n_tris > kBakeMaxTris) return FC_ERR_SHAPE;
+  if (table_bytes < fc_bake_table_bytes(n_tris)) return FC_ERR_WORKSPACE;
+  if (((uintptr_t)table & 15) != 0) return FC_ERR_RANGE;
+  return build_bake_table(verts, n_verts, tris, n_tris, (float4*)table);
+}
+
+fc_status fc_bake_sdf(const void* table, int32_t n_tris, int32_t nx, int32_t ny, int32_t nz, const float* origin,
+                      float h, float* out, void* stream) {
+  if (!table || !origin || !out) return FC_ERR_NULL;
+  if (n_tris < 4 || n_tris > kBakeMaxTris) return FC_ERR_SHAPE;
+  if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz >= (1LL << 31)) return FC_ERR_SHAPE;
+  if (!(h > 0.f) || !std::isfinite(h)) return FC_ERR_RANGE;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return FC_ERR_RANGE;
+  if (((uintptr_t)table & 15) != 0) return FC_ERR_RANGE;
+  BakeArgs b;
+  b.pos = (const float4*)table;
+  b.nrm = (const float4*)table + 3 * (size_t)n_tris;
+  b.box = (const float4*)table + (size_t)kBakeRecord * n_tris;
+  b.n_tris = n_tris;
+  b.n_clusters = (int)bake_clusters(n_tris);
+  b.nx = nx;
+  b.ny = ny;
+  b.nz = nz;
+  b.bx = (nx + 3) / 4;
+  b.by = (ny + 3) / 4;
+  b.bz = (nz + 3) / 4;
+  b.ox = origin[0];
+  b.oy = origin[1];
+  b.oz = origin[2];
+  b.h = h;
+  // The cull slack: 2^-12 of the largest node coordinate, far above the FP32
+  // rounding of the bounds and distances (a few 2^-24 of the coordinates) for
+  // any mesh inside the grid's reach.
+  double L = 0.0;
+  const int n[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a)
+    L = std::max({L, std::fabs((double)origin[a]), std::fabs((double)origin[a] + (double)h * (n[a] - 1))});
+  b.slack = (float)(L * 0x1p-12);
+  b.out = out;
+  FC_HIP(launch_bake(b, (hipStream_t)stream));
   return FC_OK;
 }
 

@@ -7,7 +7,7 @@ fails loudly when the library is not built; there is no CPU fallback.
 Names follow the C ABI: ``fc_sdf_query``, ``fc_contact_reduce``,
 ``fc_sdf_query_backward``, ``fc_sdf_query_and_backward`` (both in one pass),
 ``fc_graph_create`` / ``fc_graph_launch``,
-``fc_grid_to_bricks``, ``fc_autotune_load``.  ``Batch`` owns the device copies
+``fc_grid_to_bricks``, ``fc_bake_table`` / ``fc_bake_sdf``, ``fc_autotune_load``.  ``Batch`` owns the device copies
 of a workload's grids and meshes and the opaque ``fc_batch`` handle.
 """
 from __future__ import annotations
@@ -102,6 +102,10 @@ SIGNATURES = {
     "fc_sdf_query_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_pgd), C.POINTER(fc_candidates),
                                      C.POINTER(fc_contacts), C.c_void_p, C.c_size_t, C.c_void_p]),
     "fc_batch_face_queries": (C.c_int64, [C.c_void_p]),
+    "fc_bake_table_bytes": (C.c_size_t, [C.c_int32]),
+    "fc_bake_table": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
+    "fc_bake_sdf": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float),
+                              C.c_float, C.c_void_p, C.c_void_p]),
     "fc_status_str": (C.c_char_p, [C.c_int]),
     "fc_last_hip_error": (C.c_int32, []),
     "fc_version": (C.c_char_p, []),
@@ -376,6 +380,47 @@ def fc_sdf_query_faces(batch: Batch, pose, cand=None, fused_out=None, iters=PGD_
 def fc_gather_probe(batch: Batch, pose, sink, stream=None):
     """The one-pass kernel's loads without its arithmetic (a measurement aid)."""
     _check(lib().fc_gather_probe(batch.handle, _ptr(pose), _ptr(sink), _stream(stream)), "fc_gather_probe")
+
+
+def fc_bake_table(verts, tris) -> np.ndarray:
+    """Host table of a closed, outward-wound mesh for fc_bake_sdf: verts
+    (n, 3), tris (m, 3) -> float32 array (rows, 4) in the library's layout
+    (see fc_bake_table in include/fc.h)."""
+    v = np.ascontiguousarray(verts, dtype=np.float32)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+        raise ValueError("verts and tris must be (n, 3) and (m, 3)")
+    nb = int(lib().fc_bake_table_bytes(len(t)))
+    out = np.zeros((max(nb, 16) // 16, 4), dtype=np.float32)
+    _check(lib().fc_bake_table(v.ctypes.data_as(C.c_void_p), len(v), t.ctypes.data_as(C.c_void_p), len(t),
+                               out.ctypes.data_as(C.c_void_p), nb), "fc_bake_table")
+    return out
+
+
+class BakeTable:
+    """A bake table resident on one GPU (the host table, copied once)."""
+
+    def __init__(self, verts, tris, device="cuda"):
+        import torch
+
+        self.n_tris = int(np.asarray(tris).shape[0])
+        self.table = torch.from_numpy(fc_bake_table(verts, tris)).to(device)
+
+
+def fc_bake_sdf(table: BakeTable, dims, origin, h, out=None, stream=None):
+    """Signed distance of the table's mesh at every node: a float32 tensor
+    [nz][ny][nx] (``out`` if given)."""
+    import torch
+
+    nx, ny, nz = (int(d) for d in dims)
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=table.table.device)
+    elif out.dtype != torch.float32 or out.numel() != nx * ny * nz or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of nx*ny*nz elements")
+    o = (C.c_float * 3)(*[float(x) for x in origin])
+    _check(lib().fc_bake_sdf(_ptr(table.table), table.n_tris, nx, ny, nz, o, float(h), _ptr(out), _stream(stream)),
+           "fc_bake_sdf")
+    return out
 
 
 class Graph:

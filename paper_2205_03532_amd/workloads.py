@@ -412,6 +412,58 @@ def rect_peg(half_x, half_y, length, n_per_side) -> Mesh:
     return Mesh(verts=np.ascontiguousarray(verts[perm].astype(np.float32)))
 
 
+def bolt_mesh(P, Rmaj, L, n_theta, n_z):
+    """Closed, outward-wound threaded rod along +z, z in [0, L]: the thread
+    surface rho = r(z - P theta / (2 pi)) sampled n_theta x n_z (z from 0 to
+    L inclusive), closed by two disk fans about the axis.
+    2 n_theta (n_z - 1) + 2 n_theta triangles."""
+    th = np.arange(n_theta, dtype=np.float64) * (2.0 * math.pi / n_theta)
+    zz = np.linspace(0.0, L, n_z)
+    TH, ZZ = np.meshgrid(th, zz, indexing="ij")  # (n_theta, n_z)
+    rho = thread_profile_radius(ZZ - P * TH / (2.0 * math.pi), P, Rmaj)
+    side = np.stack([rho * np.cos(TH), rho * np.sin(TH), ZZ], axis=-1).reshape(-1, 3)
+    i = np.arange(n_theta)[:, None]
+    j = np.arange(n_z - 1)[None, :]
+    a = i * n_z + j
+    b = ((i + 1) % n_theta) * n_z + j
+    tris = [np.stack([a, b, b + 1], -1).reshape(-1, 3), np.stack([a, b + 1, a + 1], -1).reshape(-1, 3)]
+    lo, hi = n_theta * n_z, n_theta * n_z + 1  # cap centres
+    r0 = np.arange(n_theta) * n_z
+    r1 = ((np.arange(n_theta) + 1) % n_theta) * n_z
+    tris.append(np.stack([np.full(n_theta, lo), r1, r0], -1))  # z = 0, normal -z
+    tris.append(np.stack([np.full(n_theta, hi), r0 + n_z - 1, r1 + n_z - 1], -1))  # z = L, normal +z
+    verts = np.concatenate([side, [[0.0, 0.0, 0.0], [0.0, 0.0, L]]])
+    return verts.astype(np.float32), np.concatenate(tris).astype(np.int32)
+
+
+@dataclass(frozen=True)
+class BakeSpec:
+    """A mesh to bake and the grid to bake it on."""
+    name: str
+    P: float
+    Rmaj: float
+    L: float
+    n_theta: int
+    n_z: int
+    grid_dims: tuple
+    h: float
+    origin: tuple
+
+
+# An M4 bolt as a 47k-triangle mesh on a 144 x 144 x 256 grid (5.3 M nodes):
+# the size class of the M4 bolt SDF the paper describes (Appendix, geometric
+# representations); a headless threaded rod stands in for the real part.
+M4_BOLT_BAKE = BakeSpec(name="m4_bolt_bake", P=0.7e-3, Rmaj=2e-3, L=12e-3, n_theta=128, n_z=184,
+                        grid_dims=(144, 144, 256), h=0.06e-3,
+                        origin=(-4.29e-3, -4.29e-3, -1.65e-3))
+
+
+def bake_workload(spec: BakeSpec = M4_BOLT_BAKE):
+    """(verts float32 (n, 3), tris int32 (m, 3), dims, origin, h) of a bake."""
+    v, t = bolt_mesh(spec.P, spec.Rmaj, spec.L, spec.n_theta, spec.n_z)
+    return v, t, spec.grid_dims, tuple(f32(o) for o in spec.origin), f32(spec.h)
+
+
 def tetrahedron_mesh(scale=1.0):
     """Regular tetrahedron, 4 vertices, 4 outward-wound triangles."""
     v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64) * scale

@@ -1,0 +1,159 @@
+"""GPU parity of the mesh-to-SDF bake (fc_bake_sdf) against the FP64 oracle,
+through the C ABI.
+
+Tolerance: the kernel evaluates node positions, closest points and distances
+in FP32.  Every quantity is a short chain of roundings of values no larger
+than L, the largest coordinate of any node or vertex, and the distance is
+first-order insensitive to the closest point's error along the surface (the
+offset p - q is normal to the feature), so |d_gpu - d_fp64| <= c eps32 L with
+a small constant; the tests take c = 32.  The nearest triangle may differ
+where two are within that tolerance of each other (the distance does not);
+the sign is compared wherever |d| exceeds the tolerance.
+
+At the full size (an M4-class bolt, 47k triangles, 144 x 144 x 256 nodes) the
+oracle evaluates a sample of nodes; every node is checked against properties
+that hold at any size: a signed distance is 1-Lipschitz, and the sign follows
+the bolt's solid (inside the thread's root cylinder, outside its crest
+cylinder)."""
+import numpy as np
+import pytest
+
+from _gpu_common import ULP32, torch_gpu
+from oracle import bake as OB
+from paper_2205_03532_amd import fc
+from paper_2205_03532_amd import workloads as W
+from test_oracle_bake import dented_cube
+
+pytestmark = pytest.mark.gpu
+C_TOL = 32.0
+
+
+def tol_of(V, dims, origin, h):
+    far = np.abs(np.asarray(origin, np.float64)) + h * (np.asarray(dims, np.float64) - 1)
+    L = max(float(np.max(np.abs(V))), float(np.max(far)), float(np.max(np.abs(origin))))
+    return C_TOL * ULP32 * L
+
+
+def to_np(x):
+    return x.detach().cpu().numpy()
+
+
+def bake_gpu(v, t, dims, origin, h):
+    torch = torch_gpu()
+    tab = fc.BakeTable(v, t)
+    out = fc.fc_bake_sdf(tab, dims, origin, h)
+    torch.cuda.synchronize()
+    return to_np(out).astype(np.float64)
+
+
+def compare(got, ref, tol):
+    err = np.abs(got - ref)
+    assert err.max() <= tol, (err.max(), tol)
+    clear = np.abs(ref) > tol
+    assert np.array_equal(got[clear] < 0, ref[clear] < 0)
+    return float(err.max())
+
+
+CASES = {
+    # name: (mesh, dims (ragged: several 256-node blocks and a partial one), origin, h)
+    "cube": (lambda: W.cube_mesh(0.5), (13, 11, 9), (-0.9, -0.8, -0.7), 0.15),
+    "tetrahedron": (lambda: W.tetrahedron_mesh(0.5), (9, 10, 11), (-1.0, -1.0, -1.0), 0.21),
+    "dented_cube": (dented_cube, (17, 17, 17), (-0.8, -0.8, -0.8), 0.1),
+    "icosphere": (lambda: (lambda m: (m.verts, m.tris))(W.icosphere(2, 0.01)), (12, 13, 14),
+                  (-0.016, -0.016, -0.017), 0.0027),
+    "bolt": (lambda: W.bolt_mesh(0.7e-3, 2e-3, 3e-3, 24, 12), (18, 17, 21), (-3e-3, -3e-3, -1e-3), 0.25e-3),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_bake_matches_oracle(name):
+    torch_gpu()
+    mesh, dims, origin, h = CASES[name]
+    v, t = mesh()
+    v = np.asarray(v, dtype=np.float32)
+    origin = tuple(float(np.float32(o)) for o in origin)
+    h = float(np.float32(h))
+    got = bake_gpu(v, t, dims, origin, h)
+    ref = OB.bake(v.astype(np.float64), t, dims, origin, h)
+    tol = tol_of(v, dims, origin, h)
+    e = compare(got, ref, tol)
+    print(f"{name}: max |err| {e:.3e} (tol {tol:.3e}), nodes {got.size}, inside {(got < 0).sum()}")
+
+
+def test_single_node_and_single_row():
+    torch_gpu()
+    v, t = W.cube_mesh(0.5)
+    v = np.asarray(v, dtype=np.float32)
+    for dims, origin, h in (((1, 1, 1), (0.1, 0.2, 0.3), 1.0), ((300, 1, 1), (-1.0, 0.25, 0.0), 0.007)):
+        got = bake_gpu(v, t, dims, origin, h)
+        ref = OB.bake(v.astype(np.float64), t, dims, origin, h)
+        compare(got, ref, tol_of(v, dims, origin, h))
+
+
+def test_repeat_calls_and_out_argument():
+    torch = torch_gpu()
+    v, t = dented_cube()
+    tab = fc.BakeTable(v, t)
+    dims, origin, h = (20, 19, 18), (-0.8, -0.8, -0.8), 0.085
+    a = fc.fc_bake_sdf(tab, dims, origin, h)
+    out = torch.full((18, 19, 20), 7.0, dtype=torch.float32, device="cuda")
+    b = fc.fc_bake_sdf(tab, dims, origin, h, out=out)
+    torch.cuda.synchronize()
+    assert b is out
+    assert np.array_equal(to_np(a).view(np.uint32), to_np(b).view(np.uint32))
+
+
+@pytest.fixture(scope="module")
+def full_bake():
+    torch = torch_gpu()
+    v, t, dims, origin, h = W.bake_workload()
+    tab = fc.BakeTable(v, t)
+    out = fc.fc_bake_sdf(tab, dims, origin, h)
+    torch.cuda.synchronize()
+    return v, t, dims, origin, h, out
+
+
+def test_full_size_sampled_nodes_match_oracle(full_bake):
+    v, t, dims, origin, h, out = full_bake
+    nx, ny, nz = dims
+    g = to_np(out)
+    rng = np.random.default_rng(7)
+    # 200 nodes anywhere, 200 in the thread's band (by the bolt's geometry), the two corners
+    idx = rng.integers(0, g.size, 20000)
+    k, rem = np.divmod(idx, nx * ny)
+    j, i = np.divmod(rem, nx)
+    P = np.stack([origin[0] + h * i, origin[1] + h * j, origin[2] + h * k], -1)
+    rho = np.hypot(P[:, 0], P[:, 1])
+    spec = W.M4_BOLT_BAKE
+    band = (rho > spec.Rmaj - 0.6 * spec.P) & (rho < spec.Rmaj + 3 * h) & (P[:, 2] > -3 * h) & (P[:, 2] < spec.L + 3 * h)
+    idx = np.concatenate([idx[:200], idx[band][:200], [0, g.size - 1]])
+    k, rem = np.divmod(idx, nx * ny)
+    j, i = np.divmod(rem, nx)
+    P = np.stack([origin[0] + h * i, origin[1] + h * j, origin[2] + h * k], -1)
+    ref = OB.bake_points(v.astype(np.float64), t, P)
+    got = g.reshape(-1)[idx].astype(np.float64)
+    tol = tol_of(v, dims, origin, h)
+    e = compare(got, ref, tol)
+    print(f"full size: {len(idx)} sampled nodes, max |err| {e:.3e} (tol {tol:.3e})")
+
+
+def test_full_size_lipschitz_and_sign(full_bake):
+    torch = torch_gpu()
+    v, t, dims, origin, h, out = full_bake
+    tol = tol_of(v, dims, origin, h)
+    assert bool(torch.isfinite(out).all())
+    for ax in range(3):
+        d = torch.diff(out, dim=ax).abs().max().item()
+        assert d <= h * (1 + 1e-5) + 2 * tol, (ax, d, h)
+    nx, ny, nz = dims
+    x = origin[0] + h * torch.arange(nx, device=out.device, dtype=torch.float64)
+    y = origin[1] + h * torch.arange(ny, device=out.device, dtype=torch.float64)
+    z = origin[2] + h * torch.arange(nz, device=out.device, dtype=torch.float64)
+    rho = torch.sqrt(x[None, None, :] ** 2 + y[None, :, None] ** 2).expand(nz, ny, nx)
+    zz = z[:, None, None].expand(nz, ny, nx)
+    spec = W.M4_BOLT_BAKE
+    rmin = spec.Rmaj - 5.0 / 8.0 * np.sqrt(3.0) / 2.0 * spec.P
+    inside = (rho < rmin - 2 * h) & (zz > 2 * h) & (zz < spec.L - 2 * h)
+    outside = (rho > spec.Rmaj + 2 * h) | (zz < -2 * h) | (zz > spec.L + 2 * h)
+    assert bool((out[inside] < 0).all()) and bool((out[outside] > 0).all())
+    assert int(inside.sum()) > 100000 and int(outside.sum()) > 1000000
