@@ -199,6 +199,57 @@ def measure_faces(batch, pose, n, warmup):
             "samples_per_face": fc.PGD_ITERS + 1}
 
 
+def measure_bake(n, warmup, cpu_nodes):
+    """Mesh-to-SDF bake of an M4-class bolt (47,104 triangles) on a
+    144 x 144 x 256 grid: the host table (once), then fc_bake_sdf timed with
+    HIP events on the launch stream; the oracle on a few nodes, one thread."""
+    import torch
+
+    from paper_2205_03532_amd import fc
+    from paper_2205_03532_amd import workloads as W
+
+    v, t, dims, origin, h = W.bake_workload()
+    t0 = time.perf_counter()
+    table = fc.BakeTable(v, t)
+    torch.cuda.synchronize()
+    table_ms = (time.perf_counter() - t0) * 1e3
+    out = fc.fc_bake_sdf(table, dims, origin, h)
+    for _ in range(warmup):
+        fc.fc_bake_sdf(table, dims, origin, h, out=out)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        fc.fc_bake_sdf(table, dims, origin, h, out=out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    nodes = int(np.prod(dims))
+    res = {"workload": f"M4-class threaded bolt mesh ({len(t)} triangles) baked on a {'x'.join(map(str, dims))} "
+                       f"grid, h = 0.06 mm", "nodes": nodes, "triangles": int(len(t)), "kernel_ms": ms,
+           "nodes_per_s": nodes / (ms * 1e-3),
+           "brute_force_equivalent_pairs_per_s": nodes * len(t) / (ms * 1e-3),
+           "host_table_ms": table_ms}
+    if cpu_nodes > 0:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import bake as OB
+
+        rng = np.random.default_rng(11)
+        idx = rng.integers(0, nodes, cpu_nodes)
+        k, rem = np.divmod(idx, dims[0] * dims[1])
+        j, i = np.divmod(rem, dims[0])
+        P = np.stack([origin[0] + h * i, origin[1] + h * j, origin[2] + h * k], -1)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            OB.bake_points(v.astype(np.float64), t, P)
+            dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": cpu_nodes / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{cpu_nodes} random nodes against all {len(t)} triangles, FP64, "
+                                         f"one thread, {dt:.1f} s"}
+    return res
+
+
 def measure_forms(w32, device, n, warmup):
     """The other forms of the path beside the FP32 nut-bolt step: the same
     batch with FP16 and BF16 grid storage, and the uneven mixed batch
@@ -434,6 +485,7 @@ def main():
     if not args.no_forms and args.dtype == "f32":
         res["forms"] = {"nutbolt_faces_pgd": measure_faces(batch, pose, n, args.warmup)}
         res["forms"].update(measure_forms(w, dev, n, args.warmup))
+        res["forms"]["m4_bolt_mesh_bake"] = measure_bake(n, args.warmup, 0 if args.no_cpu_baseline else 100)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, w.n_env))
     print(json.dumps(res), flush=True)

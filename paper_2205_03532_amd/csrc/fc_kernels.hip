@@ -806,7 +806,9 @@ __global__ __launch_bounds__(256) void k_face_payload(FwdArgs A) {
 // ---------------------------------------------------------------------------
 // Closest point of triangle (a, a + ab, a + ac) to p and its feature, by the
 // Voronoi-region tests in the order vertex a, vertex b, edge ab, vertex c,
-// edge ac, edge bc, face (codes as BakeFeature).  Returns |p - q|^2.
+// edge ac, edge bc, face (codes as BakeFeature).  Returns |p - q|^2.  Lanes
+// leave the chain at their region, so a wave whose nodes all see a vertex or
+// an edge of a distant triangle skips the rest.
 __device__ __forceinline__ float closest_on_triangle(float px, float py, float pz, const float4& A,
                                                      const float4& AB, const float4& AC, float& qx, float& qy,
                                                      float& qz, int& feat) {
@@ -829,23 +831,24 @@ __device__ __forceinline__ float closest_on_triangle(float px, float py, float p
     u = 1.f;
     feat = kBakeVertB;
   } else if ((vc <= 0.f) & (d1 >= 0.f) & (d3 <= 0.f)) {
-    u = d1 / (d1 - d3);
+    u = d1 * __builtin_amdgcn_rcpf(d1 - d3);
     feat = kBakeEdgeAB;
   } else if ((d6 >= 0.f) & (d5 <= d6)) {
     v = 1.f;
     feat = kBakeVertC;
   } else if ((vb <= 0.f) & (d2 >= 0.f) & (d6 <= 0.f)) {
-    v = d2 / (d2 - d6);
+    v = d2 * __builtin_amdgcn_rcpf(d2 - d6);
     feat = kBakeEdgeAC;
   } else if ((va <= 0.f) & ((d4 - d3) >= 0.f) & ((d5 - d6) >= 0.f)) {
-    const float w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
-    u = 1.f - w;
-    v = w;
+    const float e43 = d4 - d3, e56 = d5 - d6;
+    const float r = __builtin_amdgcn_rcpf(e43 + e56);
+    u = e56 * r;  // 1 - w
+    v = e43 * r;  // w
     feat = kBakeEdgeBC;
   } else {
-    const float den = 1.f / ((va + vb) + vc);
-    u = vb * den;
-    v = vc * den;
+    const float r = __builtin_amdgcn_rcpf((va + vb) + vc);
+    u = vb * r;
+    v = vc * r;
     feat = kBakeFace;
   }
   qx = fmaf(v, AC.x, fmaf(u, AB.x, A.x));
@@ -875,29 +878,62 @@ __device__ __forceinline__ float box_ub2(float blx, float bly, float blz, float 
 
 struct BakeBest {
   float d2 = __builtin_inff();
+  float lim = __builtin_inff();  // (sqrt(d2) + slack)^2: a triangle whose box is farther cannot win or tie
   float qx = 0.f, qy = 0.f, qz = 0.f;
   int t = -1;                   // position in the table
   int orig = 0x7FFFFFFF;        // the mesh's triangle index (ties go to the lowest)
   int feat = 0;
 };
 
-// Every triangle of cluster c against this lane's node.  t and the records
-// are wave-uniform (scalar loads).
-__device__ __forceinline__ void bake_cluster(const BakeArgs& B, int c, float px, float py, float pz, BakeBest& b) {
-  const int t0 = c * kBakeCluster;
-  const int t1 = min(B.n_tris, t0 + kBakeCluster);
-  for (int t = t0; t < t1; ++t) {
-    const float4 A = B.pos[3 * t], AB = B.pos[3 * t + 1], AC = B.pos[3 * t + 2];
+__device__ __forceinline__ float lane_f(float x, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+}
+
+// Cluster c against this lane's node.  Lanes 0..31 (and again 32..63) load
+// one triangle each and test its bounding box against the brick's box with
+// the wave's bound.  Each triangle that passes is broadcast from the lane
+// that loaded it; the wave evaluates it only if its box is within some
+// lane's own limit.
+__device__ __forceinline__ void bake_cluster(const BakeArgs& B, int c, float blx, float bly, float blz, float bhx,
+                                             float bhy, float bhz, float bound, float slack, float px, float py,
+                                             float pz, BakeBest& b) {
+  const int t = c * kBakeCluster + (int)(threadIdx.x & (kBakeCluster - 1));
+  float4 A = make_float4(0.f, 0.f, 0.f, 0.f), AB = A, AC = A, lo = A, hi = A;
+  float tlb = __builtin_inff();
+  if (t < B.n_tris) {
+    A = B.pos[3 * t];
+    AB = B.pos[3 * t + 1];
+    AC = B.pos[3 * t + 2];
+    const float bx_ = A.x + AB.x, by_ = A.y + AB.y, bz_ = A.z + AB.z;
+    const float cx_ = A.x + AC.x, cy_ = A.y + AC.y, cz_ = A.z + AC.z;
+    lo = make_float4(fminf(A.x, fminf(bx_, cx_)), fminf(A.y, fminf(by_, cy_)), fminf(A.z, fminf(bz_, cz_)), 0.f);
+    hi = make_float4(fmaxf(A.x, fmaxf(bx_, cx_)), fmaxf(A.y, fmaxf(by_, cy_)), fmaxf(A.z, fmaxf(bz_, cz_)), 0.f);
+    tlb = box_lb2(blx, bly, blz, bhx, bhy, bhz, lo, hi);
+  }
+  unsigned long long m = __ballot(((threadIdx.x & 63) < kBakeCluster) & (t < B.n_tris) & (tlb <= bound));
+  while (m) {
+    const int j = __ffsll((long long)m) - 1;
+    m &= m - 1;
+    // this lane's distance to the triangle's box
+    const float dx = fmaxf(fmaxf(lane_f(lo.x, j) - px, px - lane_f(hi.x, j)), 0.f);
+    const float dy = fmaxf(fmaxf(lane_f(lo.y, j) - py, py - lane_f(hi.y, j)), 0.f);
+    const float dz = fmaxf(fmaxf(lane_f(lo.z, j) - pz, pz - lane_f(hi.z, j)), 0.f);
+    if (__ballot(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) <= b.lim) == 0) continue;
+    const float4 Aj = make_float4(lane_f(A.x, j), lane_f(A.y, j), lane_f(A.z, j), lane_f(A.w, j));
+    const float4 ABj = make_float4(lane_f(AB.x, j), lane_f(AB.y, j), lane_f(AB.z, j), 0.f);
+    const float4 ACj = make_float4(lane_f(AC.x, j), lane_f(AC.y, j), lane_f(AC.z, j), 0.f);
     float qx, qy, qz;
     int feat;
-    const float d2 = closest_on_triangle(px, py, pz, A, AB, AC, qx, qy, qz, feat);
-    const int orig = __float_as_int(A.w);
+    const float d2 = closest_on_triangle(px, py, pz, Aj, ABj, ACj, qx, qy, qz, feat);
+    const int orig = __float_as_int(Aj.w);
     if (d2 < b.d2 || (d2 == b.d2 && orig < b.orig)) {
       b.d2 = d2;
+      const float r = sqrtf(d2) + slack;
+      b.lim = r * r;
       b.qx = qx;
       b.qy = qy;
       b.qz = qz;
-      b.t = t;
+      b.t = c * kBakeCluster + j;
       b.orig = orig;
       b.feat = feat;
     }
@@ -957,19 +993,31 @@ __global__ __launch_bounds__(kBakeBlock) void k_bake(BakeArgs B) {
   }
   const int first = __builtin_amdgcn_readfirstlane(uc);
   BakeBest b;
-  bake_cluster(B, first, px, py, pz, b);
+  // the least upper bound plus the slack: every lane has a triangle that near
+  const float r0 = sqrtf(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ub)))) + slack;
+  bake_cluster(B, first, blx, bly, blz, bhx, bhy, bhz, r0 * r0, slack, px, py, pz, b);
   float bound = bake_bound(b.d2, slack);
 
   for (int c0 = 0; c0 < B.n_clusters; c0 += 64) {
     const int c = c0 + lane;
     float lb = __builtin_inff();
-    if (c < B.n_clusters && c != first) lb = box_lb2(blx, bly, blz, bhx, bhy, bhz, B.box[2 * c], B.box[2 * c + 1]);
+    float4 cl = make_float4(0.f, 0.f, 0.f, 0.f), ch = cl;
+    if (c < B.n_clusters && c != first) {
+      cl = B.box[2 * c];
+      ch = B.box[2 * c + 1];
+      lb = box_lb2(blx, bly, blz, bhx, bhy, bhz, cl, ch);
+    }
     unsigned long long m = __ballot((c < B.n_clusters) & (c != first) & (lb <= bound));
     while (m) {
       const int i = __ffsll((long long)m) - 1;
       m &= m - 1;
-      if (__shfl(lb, i) > bound) continue;  // the bound has shrunk since the ballot
-      bake_cluster(B, c0 + i, px, py, pz, b);
+      if (lane_f(lb, i) > bound) continue;  // the bound has shrunk since the ballot
+      // skip the cluster unless its box is within some lane's own limit
+      const float dx = fmaxf(fmaxf(lane_f(cl.x, i) - px, px - lane_f(ch.x, i)), 0.f);
+      const float dy = fmaxf(fmaxf(lane_f(cl.y, i) - py, py - lane_f(ch.y, i)), 0.f);
+      const float dz = fmaxf(fmaxf(lane_f(cl.z, i) - pz, pz - lane_f(ch.z, i)), 0.f);
+      if (__ballot(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) <= b.lim) == 0) continue;
+      bake_cluster(B, c0 + i, blx, bly, blz, bhx, bhy, bhz, bound, slack, px, py, pz, b);
       bound = bake_bound(b.d2, slack);
     }
   }
