@@ -54,12 +54,14 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
-    k_obj = os.path.join(BUILD, "fc_kernels.o")
-    a_obj = os.path.join(BUILD, "fc_api.o")
-    _run([hipcc, *DEVICE_FLAGS, "-c", os.path.join(CSRC, "fc_kernels.hip"), "-o", k_obj], verbose)
-    _run([hipcc, *HOST_FLAGS, "-c", os.path.join(CSRC, "fc_api.cpp"), "-o", a_obj], verbose)
+    objs = []
+    for src in ("fc_kernels.hip", "fc_bake.hip"):
+        objs.append(os.path.join(BUILD, src.replace(".hip", ".o")))
+        _run([hipcc, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", objs[-1]], verbose)
+    objs.append(os.path.join(BUILD, "fc_api.o"))
+    _run([hipcc, *HOST_FLAGS, "-c", os.path.join(CSRC, "fc_api.cpp"), "-o", objs[-1]], verbose)
     tmp = OUT + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", k_obj, a_obj, "-o", tmp,
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
           "-Wl,-rpath,/opt/rocm/lib"], verbose)
     os.replace(tmp, OUT)
     return OUT

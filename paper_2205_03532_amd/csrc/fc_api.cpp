@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "fc_bake.h"
 #include "fc_internal.h"
 
 using namespace fcimpl;
