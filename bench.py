@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 and mixed-batch measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates rocprof byte counters) and exit")
+    ap.add_argument("--only-bake", action="store_true",
+                    help="only time the mesh-to-SDF bake form (fc_bake_sdf) and print its JSON object")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the measured bytes per launch from rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
@@ -322,6 +324,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "launches": 3}), flush=True)
+        return
+
+    if args.only_bake:
+        print(json.dumps(measure_bake(args.steps, args.warmup, 0 if args.no_cpu_baseline else 100)), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
