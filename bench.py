@@ -252,7 +252,8 @@ def measure_bake(n, warmup, cpu_nodes):
 
 def measure_forms(w32, device, n, warmup):
     """The other forms of the path beside the FP32 nut-bolt step: the same
-    batch with FP16 and BF16 grid storage, and the uneven mixed batch
+    batch with FP16 and BF16 grid storage, with narrow-band sparse storage,
+    and the uneven mixed batch
     (4,096 envs, five part types) replayed as hipGraphs.  Queries/s of the
     one-pass step and of the fused forward; depth error of the half forms
     against the FP64 oracle on the FP32 grid (4 envs)."""
@@ -278,6 +279,28 @@ def measure_forms(w32, device, n, warmup):
             "max_depth_err_m_vs_fp32_grid_oracle": depth_check(w32, cand["phi"].cpu().numpy()),
             "launch": b.get_launch()}
         del b, o, g, cand
+    # narrow-band sparse storage of the same FP32 grid (4-voxel band): every nut
+    # query lies in a stored brick, so the outputs must equal the brick layout's
+    bs = make_batch(w32, device, layout="sparse")
+    bb = make_batch(w32, device, layout="brick")
+    pose = fc.pose_tensor(w32.pose, device)
+    outs = []
+    for b in (bs, bb):
+        o, g = b.new_contacts(), b.new_grads(per_env=False)
+        fc.fc_sdf_query_and_backward(b, pose, o, K_PENALTY, g)
+        outs.append((o, g))
+    torch.cuda.synchronize()
+    same = all(torch.equal(outs[0][0][k], outs[1][0][k]) for k in outs[0][0]) and all(
+        torch.equal(outs[0][1][k], outs[1][1][k]) for k in ("loss", "d_pose", "d_verts"))
+    o, g = outs[0]
+    ms_one = time_calls(lambda: fc.fc_sdf_query_and_backward(bs, pose, o, K_PENALTY, g), n, warmup)
+    ms_fwd = time_calls(lambda: fc.fc_sdf_query(bs, pose, fused_out=o), n, warmup)
+    out["nutbolt_f32_sparse_grid"] = {
+        "fwd_bwd_queries_per_s": bs.Q / (ms_one * 1e-3), "fwd_queries_per_s": bs.Q / (ms_fwd * 1e-3),
+        "grid_bytes": bs.sparse_bytes, "brick_grid_bytes": int(bb.grid_tensors[0].numel()),
+        "linear_grid_bytes": int(w32.grids[0].values.nbytes), "band_m": fc.SPARSE_BAND_VOXELS * w32.grids[0].h,
+        "equals_brick_layout": bool(same), "launch": bs.get_launch()}
+    del bs, bb, outs, o, g
     wm = W.mixed_workload()
     b = make_batch(wm, device)
     pose = fc.pose_tensor(wm.pose, device)

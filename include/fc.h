@@ -68,9 +68,27 @@ typedef enum fc_dtype { FC_F32 = 0, FC_F16 = 1, FC_BF16 = 2 } fc_dtype;
  *                   FP16/BF16: one 128-byte line).
  * FC_LAYOUT_SLAB:   bricks of 4x4x2 nodes covering 3x3x1 cells (FP32: one
  *                   128-byte line per cell lookup).
+ * FC_LAYOUT_SPARSE: the bricks of FC_LAYOUT_BRICK stored only near the
+ *                   surface (Section VII: sparse SDFs to cut the memory
+ *                   footprint), written by fc_grid_to_sparse.  One buffer:
+ *                   a brick map (int32 per brick: slot in the pool, -1 = not
+ *                   stored), the coarse grid of the brick-corner nodes
+ *                   (node (3i, 3j, 3k) of the linear grid), and the pool of
+ *                   stored bricks; sections start at 256-byte offsets.  A
+ *                   cell in a stored brick reads its 8 corners as in
+ *                   FC_LAYOUT_BRICK (same values, same bits of every
+ *                   result); a cell in a brick that is not stored takes the
+ *                   trilinear interpolant of the brick's 8 corner nodes
+ *                   (spacing 3h) -- value and gradient of that coarse
+ *                   interpolant, up to FP32 rounding.
  * Bricks are stored z-major, then y, then x; inside a brick x is fastest.
  * Values are copied, not rounded. */
-typedef enum fc_layout { FC_LAYOUT_LINEAR = 0, FC_LAYOUT_BRICK = 1, FC_LAYOUT_SLAB = 2 } fc_layout;
+typedef enum fc_layout {
+  FC_LAYOUT_LINEAR = 0,
+  FC_LAYOUT_BRICK = 1,
+  FC_LAYOUT_SLAB = 2,
+  FC_LAYOUT_SPARSE = 3
+} fc_layout;
 
 #define FC_MAX_TYPES 8 /* distinct grids and distinct meshes per batch */
 #define FC_MAX_BINS 64 /* normal bins K */
@@ -321,6 +339,27 @@ size_t fc_grid_brick_bytes(const fc_grid* src, int32_t layout);
  * fc_grid_brick_bytes bytes) and fills *dst with a descriptor of the result.
  * Exact copy of the values (no rounding).  Asynchronous on stream. */
 fc_status fc_grid_to_bricks(const fc_grid* src, int32_t layout, void* dst_data, size_t dst_bytes, fc_grid* dst,
+                            void* stream);
+
+/* Narrow-band sparse storage of a linear grid (FC_LAYOUT_SPARSE).  A brick
+ * (4x4x4 nodes, 3x3x3 cells, bricks of FC_LAYOUT_BRICK) is stored iff one of
+ * its nodes has |value| <= band, its nodes have both signs (value < 0 and
+ * value >= 0), or it reaches past the grid's last node on some axis.
+ * Queries whose cell lies in a stored brick give FC_LAYOUT_BRICK's results
+ * bit for bit.  A brick that is not stored has every node beyond the band on
+ * one side: outside (all > band), with margin <= band, its queries are
+ * neither candidates nor penalised in either layout; inside (all < -band)
+ * they take the coarse interpolant.  band >= 0 (+inf stores every
+ * brick; else FC_ERR_RANGE); src must be FC_LAYOUT_LINEAR (else
+ * FC_ERR_DTYPE).  Both calls are set-up calls: they allocate a temporary,
+ * run a classification kernel on `stream` and synchronise it. */
+/* *bytes = the size of the sparse buffer of src with this band. */
+fc_status fc_grid_sparse_bytes(const fc_grid* src, float band, size_t* bytes, void* stream);
+/* Write the sparse buffer to dst_data (device, 256-byte aligned, at least
+ * fc_grid_sparse_bytes bytes; else FC_ERR_RANGE / FC_ERR_WORKSPACE) and fill
+ * *dst with its descriptor (data = dst_data, layout FC_LAYOUT_SPARSE, the
+ * dims, origin and h of src).  Returns after the buffer is written. */
+fc_status fc_grid_to_sparse(const fc_grid* src, float band, void* dst_data, size_t dst_bytes, fc_grid* dst,
                             void* stream);
 
 /* ---- mesh -> SDF bake -------------------------------------------------- */

@@ -53,16 +53,18 @@ void bricks_of(const fc_grid& g, int layout, int& bx, int& by, int& bz) {
 }
 
 bool is_brick(int layout) { return layout == FC_LAYOUT_BRICK || layout == FC_LAYOUT_SLAB; }
+// layouts whose kernels address bricks (the sparse one uses FC_LAYOUT_BRICK's)
+bool has_bricks(int layout) { return is_brick(layout) || layout == FC_LAYOUT_SPARSE; }
 
 int elem_size(int dtype) { return dtype == FC_F32 ? 4 : 2; }
 
 fc_status check_grid(const fc_grid& g) {
   if (!g.data) return FC_ERR_NULL;
   if (g.dtype < FC_F32 || g.dtype > FC_BF16) return FC_ERR_DTYPE;
-  if (g.layout != FC_LAYOUT_LINEAR && !is_brick(g.layout)) return FC_ERR_DTYPE;
+  if (g.layout != FC_LAYOUT_LINEAR && !has_bricks(g.layout)) return FC_ERR_DTYPE;
   if (g.nx < 2 || g.ny < 2 || g.nz < 2) return FC_ERR_SHAPE;
   if ((long long)g.nx * g.ny * g.nz >= (1LL << 31)) return FC_ERR_SHAPE;
-  if (is_brick(g.layout)) {
+  if (has_bricks(g.layout)) {
     int bx, by, bz, nx, ny, nz;
     bricks_of(g, g.layout, bx, by, bz);
     brick_nodes(g.layout, nx, ny, nz);
@@ -130,9 +132,18 @@ GridDev to_dev(const fc_grid& g) {
   d.ny = g.ny;
   d.nz = g.nz;
   int bx = 0, by = 0, bz = 0;
-  if (is_brick(g.layout)) bricks_of(g, g.layout, bx, by, bz);
+  if (has_bricks(g.layout)) bricks_of(g, g.layout, bx, by, bz);
   d.bx = bx;
   d.by = by;
+  d.map = nullptr;
+  d.coarse = nullptr;
+  if (g.layout == FC_LAYOUT_SPARSE) {  // one buffer: map, coarse grid, pool
+    const char* base = static_cast<const char*>(g.data);
+    const long long nb = (long long)bx * by * bz;
+    d.map = reinterpret_cast<const int*>(base);
+    d.coarse = base + sparse_coarse_offset(nb);
+    d.data = base + sparse_pool_offset(nb, bx, by, bz, elem_size(g.dtype));
+  }
   d.ox = g.origin[0];
   d.oy = g.origin[1];
   d.oz = g.origin[2];
@@ -773,6 +784,52 @@ fc_status validate_backward(const fc_batch* b, const float* pose, float k, const
   return check_ws(b, ws, ws_bytes);
 }
 
+// ---- sparse grids -------------------------------------------------------------
+
+struct SparsePlan {
+  int bx = 0, by = 0, bz = 0;
+  std::vector<int> map;   // per brick: slot or -1
+  std::vector<int> list;  // per slot: brick index
+};
+
+fc_status check_sparse_args(const fc_grid* src, float band) {
+  if (!src) return FC_ERR_NULL;
+  fc_status st = check_grid(*src);
+  if (st != FC_OK) return st;
+  if (src->layout != FC_LAYOUT_LINEAR) return FC_ERR_DTYPE;
+  if (!(band >= 0.f)) return FC_ERR_RANGE;  // also NaN
+  fc_grid g = *src;
+  g.layout = FC_LAYOUT_BRICK;
+  return check_grid(g);  // the brick count must fit too
+}
+
+fc_status sparse_plan(const fc_grid& src, float band, hipStream_t s, SparsePlan& p) {
+  bricks_of(src, FC_LAYOUT_BRICK, p.bx, p.by, p.bz);
+  const long long nb = (long long)p.bx * p.by * p.bz;
+  unsigned char* d_flags = nullptr;
+  FC_HIP(hipMalloc(&d_flags, (size_t)nb));
+  std::vector<unsigned char> f((size_t)nb);
+  hipError_t e = launch_sparse_classify(src.data, src.dtype, src.nx, src.ny, src.nz, p.bx, p.by, p.bz, band, d_flags, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(f.data(), d_flags, (size_t)nb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t e2 = hipFree(d_flags);
+  if (e != hipSuccess) return hip_fail(e);
+  if (e2 != hipSuccess) return hip_fail(e2);
+  p.map.assign((size_t)nb, -1);
+  p.list.clear();
+  for (long long b = 0; b < nb; ++b)
+    if (f[(size_t)b]) {
+      p.map[(size_t)b] = (int)p.list.size();
+      p.list.push_back((int)b);
+    }
+  return FC_OK;
+}
+
+size_t sparse_bytes(const SparsePlan& p, int elem) {
+  const long long nb = (long long)p.bx * p.by * p.bz;
+  return sparse_pool_offset(nb, p.bx, p.by, p.bz, elem) + p.list.size() * 64 * (size_t)elem;
+}
+
 // ---- mesh -> SDF bake -------------------------------------------------------
 
 constexpr long long kBakeMaxTris = 1LL << 24;
@@ -1229,6 +1286,49 @@ fc_status fc_grid_to_bricks(const fc_grid* src, int32_t layout, void* dst_data, 
   *dst = *src;
   dst->data = dst_data;
   dst->layout = layout;
+  return FC_OK;
+}
+
+fc_status fc_grid_sparse_bytes(const fc_grid* src, float band, size_t* bytes, void* stream) {
+  if (!bytes) return FC_ERR_NULL;
+  fc_status st = check_sparse_args(src, band);
+  if (st != FC_OK) return st;
+  SparsePlan p;
+  st = sparse_plan(*src, band, (hipStream_t)stream, p);
+  if (st != FC_OK) return st;
+  *bytes = sparse_bytes(p, elem_size(src->dtype));
+  return FC_OK;
+}
+
+fc_status fc_grid_to_sparse(const fc_grid* src, float band, void* dst_data, size_t dst_bytes, fc_grid* dst,
+                            void* stream) {
+  if (!dst_data || !dst) return FC_ERR_NULL;
+  fc_status st = check_sparse_args(src, band);
+  if (st != FC_OK) return st;
+  if (((uintptr_t)dst_data & 255) != 0) return FC_ERR_RANGE;
+  const hipStream_t s = (hipStream_t)stream;
+  SparsePlan p;
+  st = sparse_plan(*src, band, s, p);
+  if (st != FC_OK) return st;
+  const int elem = elem_size(src->dtype);
+  if (dst_bytes < sparse_bytes(p, elem)) return FC_ERR_WORKSPACE;
+  const long long nb = (long long)p.bx * p.by * p.bz;
+  char* base = static_cast<char*>(dst_data);
+  int* d_list = nullptr;
+  if (!p.list.empty()) FC_HIP(hipMalloc(&d_list, p.list.size() * sizeof(int)));
+  hipError_t e = hipMemcpyAsync(base, p.map.data(), (size_t)nb * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && d_list)
+    e = hipMemcpyAsync(d_list, p.list.data(), p.list.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_sparse_fill(src->data, elem, src->nx, src->ny, src->nz, p.bx, p.by, p.bz, d_list, (int)p.list.size(),
+                           base + sparse_pool_offset(nb, p.bx, p.by, p.bz, elem), base + sparse_coarse_offset(nb), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t e2 = d_list ? hipFree(d_list) : hipSuccess;
+  if (e != hipSuccess) return hip_fail(e);
+  if (e2 != hipSuccess) return hip_fail(e2);
+  *dst = *src;
+  dst->data = dst_data;
+  dst->layout = FC_LAYOUT_SPARSE;
   return FC_OK;
 }
 

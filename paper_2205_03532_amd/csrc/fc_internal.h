@@ -34,6 +34,11 @@ template <>
 struct BrickShape<FC_LAYOUT_SLAB> {
   static constexpr int NX = 4, NY = 4, NZ = 2;
 };
+// Sparse: the bricks of FC_LAYOUT_BRICK, stored only near the surface.
+template <>
+struct BrickShape<FC_LAYOUT_SPARSE> {
+  static constexpr int NX = 4, NY = 4, NZ = 4;
+};
 inline void brick_nodes(int layout, int& nx, int& ny, int& nz) {
   if (layout == FC_LAYOUT_SLAB) {
     nx = BrickShape<FC_LAYOUT_SLAB>::NX, ny = BrickShape<FC_LAYOUT_SLAB>::NY, nz = BrickShape<FC_LAYOUT_SLAB>::NZ;
@@ -55,12 +60,22 @@ struct BinCell {
 };
 
 struct GridDev {
-  const void* data;
+  const void* data;     // samples; FC_LAYOUT_SPARSE: the pool of stored bricks
+  const int* map;       // FC_LAYOUT_SPARSE: [bz][by][bx] slot in the pool, -1 = not stored
+  const void* coarse;   // FC_LAYOUT_SPARSE: [bz+1][by+1][bx+1] the brick-corner nodes
   int nx, ny, nz;
-  int bx, by;  // bricks along x and y (brick layout)
+  int bx, by;  // bricks along x and y (brick layouts)
   float ox, oy, oz;
   float inv_h;
 };
+
+// Sparse grid buffer: map (int32 per brick), coarse grid, pool; each section
+// starts on a 256-byte boundary.
+inline size_t sparse_align(size_t x) { return (x + 255) & ~size_t(255); }
+inline size_t sparse_coarse_offset(long long bricks) { return sparse_align((size_t)bricks * 4); }
+inline size_t sparse_pool_offset(long long bricks, int bx, int by, int bz, int elem) {
+  return sparse_coarse_offset(bricks) + sparse_align((size_t)(bx + 1) * (by + 1) * (bz + 1) * elem);
+}
 
 struct MeshDev {
   const float* x;
@@ -204,6 +219,13 @@ hipError_t launch_query_chunked(const BwdArgs& a, const QueryExtra& q, const Fwd
 // measurement aid: k_query_backward's items, loop and corner loads, no arithmetic
 hipError_t launch_gather_probe(const BwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// Sparse conversion: flags[b] = 1 if brick b is stored (a node with
+// |value| <= band, nodes of both signs, or nodes past the grid's edge).
+hipError_t launch_sparse_classify(const void* src, int dtype, int nx, int ny, int nz, int bx, int by, int bz,
+                                  float band, unsigned char* flags, hipStream_t s);
+// pool[slot] = the 64 nodes of brick list[slot]; coarse = the brick-corner nodes
+hipError_t launch_sparse_fill(const void* src, int elem, int nx, int ny, int nz, int bx, int by, int bz,
+                              const int* list, int n_stored, void* pool, void* coarse, hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int elem, int layout, int nx, int ny, int nz, int bx, int by,
                             int bz, hipStream_t s);
 bool forward_shape_supported(int block, int vpt);

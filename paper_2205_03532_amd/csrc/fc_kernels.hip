@@ -118,6 +118,44 @@ __device__ __forceinline__ float2 ld_pair<kBF16>(const void* __restrict__ p) {
   return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
 }
 
+// Sparse grid, brick not stored: the fine cell (lx, ly, lz) of the brick's
+// 3x3x3 cells takes the values at its corners of the trilinear interpolant of
+// the brick's 8 corner nodes (the coarse grid).  Trilinear interpolation
+// reproduces a trilinear function exactly, so the cell's interpolant is the
+// coarse one (up to FP32 rounding), value and gradient.
+template <int DT>
+__device__ __forceinline__ void coarse_corners(const GridDev& g, unsigned bxi, unsigned byi, unsigned bzi,
+                                               unsigned lx, unsigned ly, unsigned lz, float c[8]) {
+  constexpr size_t E = DT == kF32 ? 4 : 2;
+  const unsigned cx = (unsigned)g.bx + 1, cxy = cx * ((unsigned)g.by + 1);
+  const char* b = static_cast<const char*>(g.coarse) + (size_t)((bzi * ((unsigned)g.by + 1) + byi) * cx + bxi) * E;
+  const float2 e00 = ld_pair<DT>(b);                        // y0 z0
+  const float2 e10 = ld_pair<DT>(b + (size_t)cx * E);        // y1 z0
+  const float2 e01 = ld_pair<DT>(b + (size_t)cxy * E);       // y0 z1
+  const float2 e11 = ld_pair<DT>(b + (size_t)(cxy + cx) * E);  // y1 z1
+  const auto third = [](unsigned k) { return k == 3u ? 1.f : (float)k * (1.f / 3.f); };  // k / 3
+  const float fx0 = third(lx), fx1 = third(lx + 1);
+  const float fy0 = third(ly), fy1 = third(ly + 1);
+  const float fz0 = third(lz), fz1 = third(lz + 1);
+  // along x: a[sx][y + 2z]
+  const float d00 = e00.y - e00.x, d10 = e10.y - e10.x, d01 = e01.y - e01.x, d11 = e11.y - e11.x;
+  const float a0[4] = {fmaf(fx0, d00, e00.x), fmaf(fx0, d10, e10.x), fmaf(fx0, d01, e01.x), fmaf(fx0, d11, e11.x)};
+  const float a1[4] = {fmaf(fx1, d00, e00.x), fmaf(fx1, d10, e10.x), fmaf(fx1, d01, e01.x), fmaf(fx1, d11, e11.x)};
+  // along y, then z
+#pragma unroll
+  for (int sx = 0; sx < 2; ++sx) {
+    const float* a = sx ? a1 : a0;
+    const float dy_z0 = a[1] - a[0], dy_z1 = a[3] - a[2];
+    const float b00 = fmaf(fy0, dy_z0, a[0]), b10 = fmaf(fy1, dy_z0, a[0]);  // z0: y0, y1
+    const float b01 = fmaf(fy0, dy_z1, a[2]), b11 = fmaf(fy1, dy_z1, a[2]);  // z1: y0, y1
+    const float u0 = b01 - b00, u1 = b11 - b10;                              // along z at y0, y1
+    c[sx + 0] = fmaf(fz0, u0, b00);
+    c[sx + 2] = fmaf(fz0, u1, b10);
+    c[sx + 4] = fmaf(fz1, u0, b00);
+    c[sx + 6] = fmaf(fz1, u1, b10);
+  }
+}
+
 // Corner order: c[a + 2b + 4c] = value at node (ix+a, iy+b, iz+c).
 template <int DT, int LAYOUT>
 __device__ __forceinline__ void gather(const GridDev& g, const Cell& cl, float c[8]) {
@@ -129,6 +167,17 @@ __device__ __forceinline__ void gather(const GridDev& g, const Cell& cl, float c
     sy = (unsigned)g.nx;
     sz = (unsigned)g.nx * (unsigned)g.ny;
     i0 = (iz * (unsigned)g.ny + iy) * (unsigned)g.nx + ix;
+  } else if constexpr (LAYOUT == FC_LAYOUT_SPARSE) {
+    const unsigned bxi = ix / 3u, byi = iy / 3u, bzi = iz / 3u;
+    const unsigned lx = ix - 3u * bxi, ly = iy - 3u * byi, lz = iz - 3u * bzi;
+    const int slot = g.map[(bzi * (unsigned)g.by + byi) * (unsigned)g.bx + bxi];
+    if (slot < 0) {
+      coarse_corners<DT>(g, bxi, byi, bzi, lx, ly, lz, c);
+      return;
+    }
+    sy = 4;
+    sz = 16;
+    i0 = (unsigned)slot * 64u + (lz * 16u + ly * 4u + lx);
   } else {
     using B = BrickShape<LAYOUT>;
     constexpr unsigned CX = B::NX - 1, CY = B::NY - 1, CZ = B::NZ - 1;
@@ -1269,6 +1318,73 @@ __global__ void k_to_bricks(const T* __restrict__ src, T* __restrict__ dst, int 
   }
 }
 
+template <int DT>
+__device__ __forceinline__ float load_value(const void* __restrict__ p, long long i) {
+  if constexpr (DT == kF32) {
+    return static_cast<const float*>(p)[i];
+  } else if constexpr (DT == kF16) {
+    return __half2float(__ushort_as_half(static_cast<const unsigned short*>(p)[i]));
+  } else {
+    return __uint_as_float((unsigned)static_cast<const unsigned short*>(p)[i] << 16);
+  }
+}
+
+// One thread per brick of 4x4x4 nodes (3x3x3 cells): stored iff a node has
+// |value| <= band, nodes of both signs occur, or the brick reaches past the
+// grid's last node (its corners would not all exist).
+template <int DT>
+__global__ void k_sparse_classify(const void* __restrict__ src, int nx, int ny, int nz, int bx, int by, int bz,
+                                  float band, unsigned char* __restrict__ flags) {
+  const long long total = (long long)bx * by * bz;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < total; b += stride) {
+    const int bxi = (int)(b % bx), byi = (int)((b / bx) % by), bzi = (int)(b / ((long long)bx * by));
+    const int x0 = 3 * bxi, y0 = 3 * byi, z0 = 3 * bzi;
+    unsigned char keep = (x0 + 3 > nx - 1) | (y0 + 3 > ny - 1) | (z0 + 3 > nz - 1);
+    if (!keep) {
+      float lo = __builtin_inff();
+      bool neg = false, nonneg = false;
+      for (int z = z0; z <= z0 + 3; ++z)
+        for (int y = y0; y <= y0 + 3; ++y)
+          for (int x = x0; x <= x0 + 3; ++x) {
+            const float v = load_value<DT>(src, ((long long)z * ny + y) * nx + x);
+            lo = fminf(lo, fabsf(v));
+            neg |= v < 0.f;
+            nonneg |= !(v < 0.f);
+          }
+      keep = (lo <= band) | (neg & nonneg);
+    }
+    flags[b] = keep;
+  }
+}
+
+// pool[slot][64] = the nodes of brick list[slot] (past the grid's edge: the
+// last node, never read); coarse[K][J][I] = node (3I, 3J, 3K) (clamped).
+template <typename T>
+__global__ void k_sparse_fill(const T* __restrict__ src, int nx, int ny, int nz, int bx, int by, int bz,
+                              const int* __restrict__ list, int n_stored, T* __restrict__ pool,
+                              T* __restrict__ coarse) {
+  const long long n_pool = (long long)n_stored * 64;
+  const long long n_coarse = (long long)(bx + 1) * (by + 1) * (bz + 1);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_pool + n_coarse; i += stride) {
+    if (i < n_pool) {
+      const long long b = list[i >> 6];
+      const int local = (int)(i & 63);
+      const int bxi = (int)(b % bx), byi = (int)((b / bx) % by), bzi = (int)(b / ((long long)bx * by));
+      const int x = min(3 * bxi + (local & 3), nx - 1);
+      const int y = min(3 * byi + ((local >> 2) & 3), ny - 1);
+      const int z = min(3 * bzi + (local >> 4), nz - 1);
+      pool[i] = src[((long long)z * ny + y) * nx + x];
+    } else {
+      const long long j = i - n_pool;
+      const int I = (int)(j % (bx + 1)), J = (int)((j / (bx + 1)) % (by + 1)), K = (int)(j / ((long long)(bx + 1) * (by + 1)));
+      const int x = min(3 * I, nx - 1), y = min(3 * J, ny - 1), z = min(3 * K, nz - 1);
+      coarse[j] = src[((long long)z * ny + y) * nx + x];
+    }
+  }
+}
+
 // Optional HIP events around the main kernel of the launch in progress (set
 // by the launch_* entry points for the calling thread; see KernelMarks).
 thread_local const KernelMarks* t_marks = nullptr;
@@ -1330,6 +1446,8 @@ hipError_t fwd_layout(const FwdArgs& a, int layout, int block, int vpt, int pers
     return fwd_block<DT, FC_LAYOUT_BRICK>(a, block, vpt, persistent, xcd, grid, from_cand, s);
   if (layout == FC_LAYOUT_SLAB)
     return fwd_block<DT, FC_LAYOUT_SLAB>(a, block, vpt, persistent, xcd, grid, from_cand, s);
+  if (layout == FC_LAYOUT_SPARSE)
+    return fwd_block<DT, FC_LAYOUT_SPARSE>(a, block, vpt, persistent, xcd, grid, from_cand, s);
   return fwd_block<DT, FC_LAYOUT_LINEAR>(a, block, vpt, persistent, xcd, grid, from_cand, s);
 }
 
@@ -1399,6 +1517,7 @@ template <int DT>
 hipError_t probe_layout(const BwdArgs& a, int layout, hipStream_t s) {
   if (layout == FC_LAYOUT_BRICK) return probe_launch<DT, FC_LAYOUT_BRICK>(a, s);
   if (layout == FC_LAYOUT_SLAB) return probe_launch<DT, FC_LAYOUT_SLAB>(a, s);
+  if (layout == FC_LAYOUT_SPARSE) return probe_launch<DT, FC_LAYOUT_SPARSE>(a, s);
   return probe_launch<DT, FC_LAYOUT_LINEAR>(a, s);
 }
 
@@ -1419,6 +1538,7 @@ template <int DT>
 hipError_t qchunk_layout(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, int layout, hipStream_t s) {
   if (layout == FC_LAYOUT_BRICK) return qchunk_launch<DT, FC_LAYOUT_BRICK>(a, q, f, s);
   if (layout == FC_LAYOUT_SLAB) return qchunk_launch<DT, FC_LAYOUT_SLAB>(a, q, f, s);
+  if (layout == FC_LAYOUT_SPARSE) return qchunk_launch<DT, FC_LAYOUT_SPARSE>(a, q, f, s);
   return qchunk_launch<DT, FC_LAYOUT_LINEAR>(a, q, f, s);
 }
 
@@ -1426,6 +1546,7 @@ template <int DT>
 hipError_t qbwd_layout(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, int layout, hipStream_t s) {
   if (layout == FC_LAYOUT_BRICK) return qbwd_launch<DT, FC_LAYOUT_BRICK>(a, q, f, s);
   if (layout == FC_LAYOUT_SLAB) return qbwd_launch<DT, FC_LAYOUT_SLAB>(a, q, f, s);
+  if (layout == FC_LAYOUT_SPARSE) return qbwd_launch<DT, FC_LAYOUT_SPARSE>(a, q, f, s);
   return qbwd_launch<DT, FC_LAYOUT_LINEAR>(a, q, f, s);
 }
 
@@ -1433,6 +1554,7 @@ template <int DT>
 hipError_t bwd_layout(const BwdArgs& a, int layout, hipStream_t s) {
   if (layout == FC_LAYOUT_BRICK) return bwd_launch<DT, FC_LAYOUT_BRICK>(a, s);
   if (layout == FC_LAYOUT_SLAB) return bwd_launch<DT, FC_LAYOUT_SLAB>(a, s);
+  if (layout == FC_LAYOUT_SPARSE) return bwd_launch<DT, FC_LAYOUT_SPARSE>(a, s);
   return bwd_launch<DT, FC_LAYOUT_LINEAR>(a, s);
 }
 
@@ -1460,6 +1582,7 @@ template <int DT>
 int bwd_occupancy_layout(int layout) {
   if (layout == FC_LAYOUT_BRICK) return bwd_occupancy<DT, FC_LAYOUT_BRICK>();
   if (layout == FC_LAYOUT_SLAB) return bwd_occupancy<DT, FC_LAYOUT_SLAB>();
+  if (layout == FC_LAYOUT_SPARSE) return bwd_occupancy<DT, FC_LAYOUT_SPARSE>();
   return bwd_occupancy<DT, FC_LAYOUT_LINEAR>();
 }
 
@@ -1543,6 +1666,7 @@ template <int DT>
 hipError_t faces_layout(const FwdArgs& a, int layout, hipStream_t s) {
   if (layout == FC_LAYOUT_BRICK) return faces_launch<DT, FC_LAYOUT_BRICK>(a, s);
   if (layout == FC_LAYOUT_SLAB) return faces_launch<DT, FC_LAYOUT_SLAB>(a, s);
+  if (layout == FC_LAYOUT_SPARSE) return faces_launch<DT, FC_LAYOUT_SPARSE>(a, s);
   return faces_launch<DT, FC_LAYOUT_LINEAR>(a, s);
 }
 
@@ -1574,6 +1698,37 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   size_t blocks = (n32 + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<unsigned*>(p), n32);
+  return hipGetLastError();
+}
+
+hipError_t launch_sparse_classify(const void* src, int dtype, int nx, int ny, int nz, int bx, int by, int bz,
+                                  float band, unsigned char* flags, hipStream_t s) {
+  const long long total = (long long)bx * by * bz;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65535) blocks = 65535;
+  if (blocks < 1) blocks = 1;
+  switch (dtype) {
+    case kF32: hipLaunchKernelGGL(k_sparse_classify<kF32>, dim3((unsigned)blocks), dim3(256), 0, s, src, nx, ny, nz, bx, by, bz, band, flags); break;
+    case kF16: hipLaunchKernelGGL(k_sparse_classify<kF16>, dim3((unsigned)blocks), dim3(256), 0, s, src, nx, ny, nz, bx, by, bz, band, flags); break;
+    case kBF16: hipLaunchKernelGGL(k_sparse_classify<kBF16>, dim3((unsigned)blocks), dim3(256), 0, s, src, nx, ny, nz, bx, by, bz, band, flags); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sparse_fill(const void* src, int elem, int nx, int ny, int nz, int bx, int by, int bz,
+                              const int* list, int n_stored, void* pool, void* coarse, hipStream_t s) {
+  const long long total = (long long)n_stored * 64 + (long long)(bx + 1) * (by + 1) * (bz + 1);
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65535) blocks = 65535;
+  if (blocks < 1) blocks = 1;
+  if (elem == 4)
+    hipLaunchKernelGGL(k_sparse_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const float*>(src),
+                       nx, ny, nz, bx, by, bz, list, n_stored, static_cast<float*>(pool), static_cast<float*>(coarse));
+  else
+    hipLaunchKernelGGL(k_sparse_fill<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const uint16_t*>(src), nx, ny, nz, bx, by, bz, list, n_stored,
+                       static_cast<uint16_t*>(pool), static_cast<uint16_t*>(coarse));
   return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ LIB_PATH = os.environ.get("FC_LIB_PATH") or os.path.join(os.path.dirname(os.path
 
 FC_OK, FC_ERR_NULL, FC_ERR_SHAPE, FC_ERR_DTYPE, FC_ERR_RANGE, FC_ERR_WORKSPACE, FC_ERR_HIP, FC_ERR_UNSUPPORTED = range(8)
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
-LAYOUTS = {"linear": 0, "brick": 1, "slab": 2}
+LAYOUTS = {"linear": 0, "brick": 1, "slab": 2, "sparse": 3}
+SPARSE_BAND_VOXELS = 4.0  # default narrow band of the sparse layout, in voxels
 MAX_TYPES = 8
 MAX_BINS = 64
 
@@ -102,6 +103,9 @@ SIGNATURES = {
     "fc_sdf_query_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_pgd), C.POINTER(fc_candidates),
                                      C.POINTER(fc_contacts), C.c_void_p, C.c_size_t, C.c_void_p]),
     "fc_batch_face_queries": (C.c_int64, [C.c_void_p]),
+    "fc_grid_sparse_bytes": (C.c_int, [C.POINTER(fc_grid), C.c_float, C.POINTER(C.c_size_t), C.c_void_p]),
+    "fc_grid_to_sparse": (C.c_int, [C.POINTER(fc_grid), C.c_float, C.c_void_p, C.c_size_t, C.POINTER(fc_grid),
+                                    C.c_void_p]),
     "fc_bake_table_bytes": (C.c_size_t, [C.c_int32]),
     "fc_bake_table": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "fc_bake_sdf": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float),
@@ -164,7 +168,7 @@ class Batch:
     """
 
     def __init__(self, grids, meshes, env_grid, env_mesh, bins, margin, device="cuda", layout="linear",
-                 env_order=None):
+                 env_order=None, band=None):
         import torch
 
         L = lib()
@@ -183,7 +187,10 @@ class Batch:
             nz, ny, nx = vals.shape
             d = fc_grid(C.c_void_p(t.data_ptr()), DTYPES[g.dtype], 0, nx, ny, nz,
                         (C.c_float * 3)(*[float(np.float32(o)) for o in g.origin]), float(np.float32(g.h)))
-            if layout != "linear":
+            if layout == "sparse":
+                bnd = float(np.float32(SPARSE_BAND_VOXELS * g.h if band is None else band))
+                t, d = self._to_sparse(t, d, bnd)
+            elif layout != "linear":
                 lay = LAYOUTS[layout]
                 nb = L.fc_grid_brick_bytes(C.byref(d), lay)
                 if nb == 0:
@@ -237,10 +244,24 @@ class Batch:
         if self.workspace.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
 
+    def _to_sparse(self, t, d, band):
+        """fc_grid_to_sparse of the linear grid tensor t (descriptor d)."""
+        import torch
+
+        L = lib()
+        nb = C.c_size_t()
+        _check(L.fc_grid_sparse_bytes(C.byref(d), band, C.byref(nb), _stream(None)), "fc_grid_sparse_bytes")
+        bt = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+        out = fc_grid()
+        _check(L.fc_grid_to_sparse(C.byref(d), band, C.c_void_p(bt.data_ptr()), int(nb.value), C.byref(out),
+                                   _stream(None)), "fc_grid_to_sparse")
+        self.sparse_bytes = getattr(self, "sparse_bytes", 0) + int(nb.value)
+        return bt, out
+
     @classmethod
-    def from_workload(cls, w, device="cuda", layout="linear", env_order=None):
+    def from_workload(cls, w, device="cuda", layout="linear", env_order=None, band=None):
         return cls(w.grids, w.meshes, w.env_grid, w.env_mesh, w.bins, w.margin, device=device, layout=layout,
-                   env_order=env_order)
+                   env_order=env_order, band=band)
 
     def __del__(self):
         h = getattr(self, "handle", None)

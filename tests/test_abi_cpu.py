@@ -128,6 +128,26 @@ def test_brick_size_query(L):
     assert L.fc_grid_brick_bytes(C.byref(g), 1) == 0
 
 
+def test_sparse_conversion_rejects_invalid_arguments(L):
+    """Every check happens before the classification kernel: no HIP call here."""
+    g = fc.fc_grid(C.c_void_p(FAKE), 0, 0, 64, 64, 64, (C.c_float * 3)(0, 0, 0), 1e-3)
+    nb = C.c_size_t()
+    out = fc.fc_grid()
+    assert L.fc_grid_sparse_bytes(None, 1e-3, C.byref(nb), None) == fc.FC_ERR_NULL
+    assert L.fc_grid_sparse_bytes(C.byref(g), 1e-3, None, None) == fc.FC_ERR_NULL
+    assert L.fc_grid_sparse_bytes(C.byref(g), -1e-3, C.byref(nb), None) == fc.FC_ERR_RANGE
+    assert L.fc_grid_sparse_bytes(C.byref(g), float("nan"), C.byref(nb), None) == fc.FC_ERR_RANGE
+    assert L.fc_grid_to_sparse(C.byref(g), 1e-3, None, 1 << 20, C.byref(out), None) == fc.FC_ERR_NULL
+    assert L.fc_grid_to_sparse(C.byref(g), 1e-3, C.c_void_p(FAKE), 1 << 20, None, None) == fc.FC_ERR_NULL
+    assert L.fc_grid_to_sparse(C.byref(g), 1e-3, C.c_void_p(FAKE + 16), 1 << 20, C.byref(out), None) == fc.FC_ERR_RANGE
+    g.layout = 1  # only a linear grid converts
+    assert L.fc_grid_sparse_bytes(C.byref(g), 1e-3, C.byref(nb), None) == fc.FC_ERR_DTYPE
+    g.layout, g.nx = 0, 1
+    assert L.fc_grid_sparse_bytes(C.byref(g), 1e-3, C.byref(nb), None) == fc.FC_ERR_SHAPE
+    g.nx, g.h = 64, 0.0
+    assert L.fc_grid_sparse_bytes(C.byref(g), 1e-3, C.byref(nb), None) == fc.FC_ERR_RANGE
+
+
 def test_autotune_cache_parse(L, tmp_path):
     p = tmp_path / "tune.json"
     p.write_text(json.dumps({"entries": [

@@ -1,0 +1,190 @@
+"""GPU parity of the narrow-band sparse grid (FC_LAYOUT_SPARSE) through the
+C ABI.
+
+A query whose cell lies in a stored brick must give the brick layout's
+results bit for bit (same corner values, same arithmetic).  A query in a
+brick that is not stored takes the coarse interpolant of the brick's corner
+nodes: its phi is compared with the FP64 oracle (oracle/sparse.py) within
+the FP32 tolerance of the dense path, its normal within NORMAL_TOL_COARSE.
+Queries within the FP32 position error of a brick face may fall on either
+side and are left out of those two comparisons."""
+import numpy as np
+import pytest
+
+from _gpu_common import (DEPTH_TOL_F32, FACE_BAND, assert_same, check_bins_exact, check_reduction_exact,
+                         oracle_rows, position_error_voxels, rows_of, to_np, torch_gpu)
+from oracle import query as OQ
+from oracle import sparse as OS
+from paper_2205_03532_amd import fc
+from paper_2205_03532_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+NORMAL_TOL_COARSE = 1e-5  # chord: the coarse interpolant's normal, FP32 expansion and position rounding
+
+
+def run(batch, pose):
+    torch = torch_gpu()
+    c, o = batch.new_candidates(), batch.new_contacts()
+    fc.fc_sdf_query(batch, pose, cand=c)
+    fc.fc_sdf_query(batch, pose, fused_out=o)
+    torch.cuda.synchronize()
+    return to_np(c), to_np(o)
+
+
+def run_one_pass(batch, pose, k=1e4):
+    torch = torch_gpu()
+    o, g = batch.new_contacts(), batch.new_grads(per_env=False)
+    fc.fc_sdf_query_and_backward(batch, pose, o, k, g)
+    torch.cuda.synchronize()
+    return to_np(o), to_np(g)
+
+
+def sparse_oracle(w, envs, band):
+    """Oracle rows with phi, grad, normal, bin replaced by the sparse field's,
+    plus the stored flag and a flag for rows near a brick face."""
+    o = oracle_rows(w, envs)
+    stored = np.zeros(len(o["phi"]), bool)
+    for e in envs:
+        sel = o["env"] == e
+        g = w.grids[int(w.env_grid[e])]
+        vals = OQ.grid_values_f64(g.values, g.dtype)
+        phi, grad, ins, st = OS.sample_sparse(vals, g.origin, g.h, g.dims, o["x_b"][sel], band)
+        o["phi"][sel], o["grad"][sel], stored[sel] = phi, grad, st
+    o["normal"], o["bin"], o["dots"] = OQ.normals_and_bins(o["grad"], w.bins)
+    du = np.max(position_error_voxels(o), axis=1)
+    bandv = np.maximum(FACE_BAND, 2.0 * du)[:, None]
+    r = o["u"] - 3.0 * np.floor(o["u"] / 3.0)  # position inside the brick, in cells
+    near_brick_face = np.any((r < bandv) | (r > 3.0 - bandv), axis=1)
+    o["stored"], o["near_brick_face"] = stored, near_brick_face
+    return o
+
+
+def test_nutbolt_sparse_equals_brick():
+    """Nut vertices near the bolt lie in stored bricks (4-voxel band); the
+    others (the hex corners) lie in exterior bricks whose nodes all exceed the
+    band.  So per-query candidates equal the brick layout's in stored bricks,
+    the rest are never candidates in either layout, and the reduced contacts
+    and the one-pass adjoint equal the brick layout's bit for bit, at a
+    fraction of the memory."""
+    torch_gpu()
+    w = W.subset(W.nut_bolt_workload(), range(0, 1000, 10))
+    envs = list(range(w.n_env))
+    band = float(np.float32(4 * w.grids[0].h))
+    g = w.grids[0]
+    vals = OQ.grid_values_f64(g.values, g.dtype)
+    o = sparse_oracle(w, envs, band)
+    ins = o["inside"]
+    assert np.all(o["phi"][ins & ~o["stored"]] > band)  # unstored: exterior only
+    assert (ins & o["stored"]).sum() > 0.99 * ins.sum()
+    b_sp = fc.Batch.from_workload(w, layout="sparse", band=band)
+    b_br = fc.Batch.from_workload(w, layout="brick")
+    pose = fc.pose_tensor(w.pose)
+    c1, o1 = run(b_sp, pose)
+    c2, o2 = run(b_br, pose)
+    rows = rows_of(w, envs)
+    st = ins & o["stored"] & ~o["near_brick_face"]
+    for k in ("phi", "bin"):
+        assert np.array_equal(c1[k][rows][st].view(np.uint8), c2[k][rows][st].view(np.uint8)), k
+    assert np.array_equal(c1["normal"][:, rows][:, st].view(np.uint32), c2["normal"][:, rows][:, st].view(np.uint32))
+    ex = ins & ~o["stored"]
+    assert np.all(c1["bin"][rows][ex] == -1) and np.all(c1["phi"][rows][ex] > band)
+    assert_same(o1, o2)
+    p1, g1 = run_one_pass(b_sp, pose)
+    p2, g2 = run_one_pass(b_br, pose)
+    assert_same(p1, p2)
+    assert_same(g1, g2)
+    # the library's classification: its buffer size is the oracle's count of stored bricks
+    bx, by, bz = OS.brick_counts(g.dims)
+    n_stored = 0
+    for k in range(bz):
+        j, i = np.meshgrid(np.arange(by), np.arange(bx), indexing="ij")
+        n_stored += int(OS.brick_stored(vals, band, np.stack([i.ravel(), j.ravel(), np.full(i.size, k)], -1)).sum())
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert b_sp.sparse_bytes == al(bx * by * bz * 4) + al((bx + 1) * (by + 1) * (bz + 1) * 4) + n_stored * 64 * 4
+    brick_bytes = b_br.grid_tensors[0].numel()
+    print(f"nut-bolt sparse: {b_sp.sparse_bytes / 2**20:.1f} MiB vs brick {brick_bytes / 2**20:.1f} MiB, "
+          f"linear {g.values.nbytes / 2**20:.1f} MiB")
+    assert b_sp.sparse_bytes < brick_bytes / 4
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_half_sparse_equals_brick(dtype):
+    torch_gpu()
+    w = W.half_storage(W.subset(W.nut_bolt_workload(), range(0, 1000, 40)), dtype)
+    band = float(np.float32(4 * w.grids[0].h))
+    pose = fc.pose_tensor(w.pose)
+    c1, o1 = run(fc.Batch.from_workload(w, layout="sparse", band=band), pose)
+    c2, o2 = run(fc.Batch.from_workload(w, layout="brick"), pose)
+    assert_same(o1, o2)
+    # |phi| <= band needs a corner within the band or corners of both signs: a stored brick
+    near = np.abs(c2["phi"]) < band * (1 - 1e-6)
+    assert near.sum() > 0.9 * np.isfinite(c2["phi"]).sum()
+    assert np.array_equal(c1["phi"][near].view(np.uint32), c2["phi"][near].view(np.uint32))
+    assert np.array_equal(c1["bin"], c2["bin"])
+
+
+def test_torus_sparse_matches_oracle():
+    """Icosphere vertices spread through the torus grid: with a 1.5-voxel band
+    many queries fall in bricks that are not stored (coarse interpolant)."""
+    torch_gpu()
+    w = W.subset(W.torus_workload(), range(64))
+    envs = list(range(w.n_env))
+    band = float(np.float32(1.5 * w.grids[0].h))
+    pose = fc.pose_tensor(w.pose)
+    b_sp = fc.Batch.from_workload(w, layout="sparse", band=band)
+    c_sp, o_sp = run(b_sp, pose)
+    c_br, _ = run(fc.Batch.from_workload(w, layout="brick"), pose)
+    o = sparse_oracle(w, envs, band)
+    rows = rows_of(w, envs)
+    ins = o["inside"] & np.isfinite(c_sp["phi"][rows])
+    clear = ins & ~o["near_brick_face"]
+    st, co = clear & o["stored"], clear & ~o["stored"]
+    assert st.sum() > 10000 and co.sum() > 10000, (st.sum(), co.sum())
+    # stored bricks: the brick layout's bits
+    for k in ("phi", "bin"):
+        assert np.array_equal(c_sp[k][rows][st].view(np.uint8), c_br[k][rows][st].view(np.uint8)), k
+    assert np.array_equal(c_sp["normal"][:, rows][:, st].view(np.uint32), c_br["normal"][:, rows][:, st].view(np.uint32))
+    # coarse bricks: the oracle's coarse interpolant
+    phi = c_sp["phi"][rows].astype(np.float64)
+    err = np.abs(phi[co] - o["phi"][co])
+    assert err.max() <= DEPTH_TOL_F32, err.max()
+    nrm = c_sp["normal"][:, rows].T.astype(np.float64)
+    gl = np.linalg.norm(o["grad"], axis=1)
+    ok = co & (gl > 0.1)
+    nerr = np.linalg.norm(nrm[ok] - o["normal"][ok], axis=1)
+    assert nerr.max() <= NORMAL_TOL_COARSE, nerr.max()
+    # candidates, bins and the reduction, whatever the path
+    m = np.float64(np.float32(w.margin))
+    amb = np.abs(o["phi"] - m) <= DEPTH_TOL_F32
+    g_cand = c_sp["bin"][rows] >= 0
+    o_cand = ins & (o["phi"] < m)
+    assert not ((g_cand != o_cand) & clear & ~amb).any()
+    check_bins_exact(w, c_sp, envs)
+    check_reduction_exact(w, c_sp, o_sp, envs)
+    print(f"torus sparse: stored {st.sum()}, coarse {co.sum()}, max coarse depth err {err.max():.2e}, "
+          f"max coarse normal err {nerr.max():.2e}, bytes {b_sp.sparse_bytes}")
+
+
+def test_infinite_band_equals_brick_everywhere():
+    torch_gpu()
+    w = W.subset(W.torus_workload(), range(32))
+    pose = fc.pose_tensor(w.pose)
+    c1, o1 = run(fc.Batch.from_workload(w, layout="sparse", band=float("inf")), pose)
+    c2, o2 = run(fc.Batch.from_workload(w, layout="brick"), pose)
+    assert_same(c1, c2)
+    assert_same(o1, o2)
+
+
+def test_faces_on_sparse_equal_brick():
+    torch = torch_gpu()
+    w = W.subset(W.nut_bolt_workload(), range(0, 1000, 125))
+    band = float(np.float32(4 * w.grids[0].h))
+    pose = fc.pose_tensor(w.pose)
+    outs = []
+    for b in (fc.Batch.from_workload(w, layout="sparse", band=band), fc.Batch.from_workload(w, layout="brick")):
+        c, o = b.new_face_candidates(), b.new_contacts()
+        fc.fc_sdf_query_faces(b, pose, cand=c, fused_out=o)
+        torch.cuda.synchronize()
+        outs.append((to_np(c), to_np(o)))
+    assert_same(outs[0][0], outs[1][0])
+    assert_same(outs[0][1], outs[1][1])
