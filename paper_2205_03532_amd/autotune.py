@@ -120,7 +120,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="nutbolt", choices=["nutbolt", "mixed", "torus"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--layout", default="brick", choices=["linear", "brick", "slab"])
+    ap.add_argument("--layout", default="brick", choices=["linear", "brick", "slab", "sparse"])
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
