@@ -250,6 +250,28 @@ def measure_bake(n, warmup, cpu_nodes):
     return res
 
 
+def measure_patches(batch, pose, n, warmup):
+    """Patch reduction (Algorithm 1, fc_contact_patches) on the bench batch:
+    environments per second, patches per environment, the kernel's time."""
+    import torch
+
+    from paper_2205_03532_amd import fc
+
+    out = batch.new_patches(fc.PATCH_MAX)
+    call = lambda: fc.fc_contact_patches(batch, pose, out)  # noqa: E731
+    ms = time_calls(call, n, warmup)
+    batch.set_timing(n)
+    for _ in range(n):
+        call()
+    k, _ = batch.read_timing()
+    batch.set_timing(0)
+    torch.cuda.synchronize()
+    cnt = out["count"].cpu().numpy()
+    return {"envs_per_s": batch.n_env / (ms * 1e-3), "queries_per_s": batch.Q / (ms * 1e-3), "call_ms": ms,
+            "k_patches_ms": float(k.mean()), "max_patches": fc.PATCH_MAX, "cos_sim": fc.PATCH_COS,
+            "batch_vertices": 1024, "patches_per_env_mean": float(cnt.mean()), "patches_per_env_max": int(cnt.max())}
+
+
 def measure_forms(w32, device, n, warmup):
     """The other forms of the path beside the FP32 nut-bolt step: the same
     batch with FP16 and BF16 grid storage, with narrow-band sparse storage,
@@ -512,7 +534,8 @@ def main():
         },
     }
     if not args.no_forms and args.dtype == "f32":
-        res["forms"] = {"nutbolt_faces_pgd": measure_faces(batch, pose, n, args.warmup)}
+        res["forms"] = {"nutbolt_faces_pgd": measure_faces(batch, pose, n, args.warmup),
+                        "nutbolt_patch_reduction": measure_patches(batch, pose, n, args.warmup)}
         res["forms"].update(measure_forms(w, dev, n, args.warmup))
         res["forms"]["m4_bolt_mesh_bake"] = measure_bake(n, args.warmup, 0 if args.no_cpu_baseline else 100)
     if not args.no_cpu_baseline:

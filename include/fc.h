@@ -303,6 +303,45 @@ fc_status fc_sdf_query_faces(const fc_batch* batch, const float* pose, const fc_
  * n_tris), or -1 for NULL. */
 int64_t fc_batch_face_queries(const fc_batch* batch);
 
+/* Patch reduction, Section III-C, Algorithm 1.  Per environment, starting
+ * with no patches, for each batch of 1024 vertices (vertices [1024 k,
+ * 1024 k + 1024)): Generate the candidates (the vertex queries, phi < margin,
+ * their normals and depths bit for bit as fc_sdf_query computes them);
+ * Assign each to the patch of largest normal similarity among the patches
+ * present when the batch began, if any is similar; then while candidates
+ * remain: FindDeepest (largest depth, lowest vertex on ties), BinReduce (a
+ * new patch takes it and every remaining candidate similar to its normal),
+ * AddPatch (appended while fewer than max_patches exist; otherwise it replaces
+ * the existing patch of largest similarity with it, lowest index on ties, iff
+ * members * depth of the deepest member is larger, in FP32 -- the member
+ * count standing for the patch's area; else it is dropped).
+ * similar(a, b): (a.x b.x + a.y b.y) + a.z b.z >= cos_sim in FP32 without
+ * fused multiply-adds.  A patch keeps its founding contact's normal, its
+ * deepest member and its member count. */
+typedef struct fc_patch_params {
+  int32_t max_patches; /* N, 1 <= N <= 256 (the paper: 128 <= N <= 256) */
+  float cos_sim;       /* finite; e.g. cos(10 deg) */
+} fc_patch_params;
+/* Outputs (device), slot s = e * N + p for patch p of env e, p < count[e]
+ * (empty slots: founder = vidx = -1, the rest 0):
+ *   count[e]   patches of env e;
+ *   founder    vertex that founded the patch;  normal [3][n_env N] its normal;
+ *   vidx, depth, point [3][n_env N]: the deepest member (x_B);
+ *   members    candidates the patch holds. */
+typedef struct fc_patches {
+  int32_t* count;
+  int32_t* founder;
+  float* normal;
+  int32_t* vidx;
+  float* depth;
+  float* point;
+  int32_t* members;
+} fc_patches;
+/* One workgroup per environment; no workspace.  Errors: FC_ERR_NULL (any
+ * pointer), FC_ERR_RANGE (max_patches or cos_sim), FC_ERR_HIP. */
+fc_status fc_contact_patches(const fc_batch* batch, const float* pose, const fc_patch_params* params,
+                             const fc_patches* out, void* stream);
+
 /* fc_sdf_query with fused_out, then fc_sdf_query_backward, computed in one
  * pass over the queries: each query is located, gathered and interpolated
  * once and feeds both the contact reduction and the penalty adjoint.  Every
@@ -428,7 +467,7 @@ int32_t fc_batch_signature(const fc_batch* batch, char* buf, int32_t cap);
 /* Per-launch timing of the main kernels.  After fc_batch_set_timing(batch, n)
  * the next n compute calls on this batch (fc_sdf_query, fc_contact_reduce,
  * fc_sdf_query_backward, fc_sdf_query_and_backward, fc_sdf_query_faces,
- * fc_gather_probe; not graph capture or
+ * fc_contact_patches, fc_gather_probe; not graph capture or
  * replay) record a pair of HIP events on their stream right before and right
  * after their main kernel, leaving out the small payload / combine kernels
  * that follow it.  n = 0 turns timing off; 0 <= n <= FC_MAX_TIMING_RECORDS
@@ -440,7 +479,8 @@ typedef enum fc_kernel_id {
   FC_KERNEL_BACKWARD = 1,       /* k_backward */
   FC_KERNEL_QUERY_BACKWARD = 2, /* k_query_backward */
   FC_KERNEL_GATHER_PROBE = 3,   /* k_gather_probe */
-  FC_KERNEL_FACES = 4           /* k_faces */
+  FC_KERNEL_FACES = 4,          /* k_faces */
+  FC_KERNEL_PATCHES = 5         /* k_patches */
 } fc_kernel_id;
 fc_status fc_batch_set_timing(fc_batch* batch, int32_t max_records);
 /* Waits for the recorded launches and writes, for the first min(recorded,

@@ -659,9 +659,11 @@ FwdArgs make_fwd(const fc_batch* b, const float* pose, const fc_candidates* cand
     a.o_nrm = out->normal;
     a.o_count = out->count;
   }
-  char* w = static_cast<char*>(ws);
-  a.keys = reinterpret_cast<unsigned long long*>(w + b->off_keys);
-  a.work_ctr = reinterpret_cast<unsigned*>(w + b->off_workctr);
+  if (ws) {  // calls without a workspace (patches) use neither
+    char* w = static_cast<char*>(ws);
+    a.keys = reinterpret_cast<unsigned long long*>(w + b->off_keys);
+    a.work_ctr = reinterpret_cast<unsigned*>(w + b->off_workctr);
+  }
   return a;
 }
 
@@ -1184,6 +1186,28 @@ fc_status fc_sdf_query_faces(const fc_batch* b, const float* pose, const fc_pgd*
 }
 
 int64_t fc_batch_face_queries(const fc_batch* b) { return b ? b->Qf : -1; }
+
+fc_status fc_contact_patches(const fc_batch* b, const float* pose, const fc_patch_params* prm, const fc_patches* out,
+                             void* stream) {
+  if (!b || !pose || !prm || !out) return FC_ERR_NULL;
+  if (!out->count || !out->founder || !out->normal || !out->vidx || !out->depth || !out->point || !out->members)
+    return FC_ERR_NULL;
+  if (prm->max_patches < 1 || prm->max_patches > kPatchMax || !std::isfinite(prm->cos_sim)) return FC_ERR_RANGE;
+  FwdArgs a = make_fwd(b, pose, nullptr, nullptr, nullptr);
+  PatchArgs p;
+  p.n_max = prm->max_patches;
+  p.cos_sim = prm->cos_sim;
+  p.count = out->count;
+  p.founder = out->founder;
+  p.normal = out->normal;
+  p.vidx = out->vidx;
+  p.depth = out->depth;
+  p.point = out->point;
+  p.members = out->members;
+  KernelMarks m;
+  FC_HIP(launch_patches(a, p, b->dtype, b->layout, (hipStream_t)stream, take_marks(b, FC_KERNEL_PATCHES, true, m)));
+  return FC_OK;
+}
 
 fc_status fc_gather_probe(const fc_batch* b, const float* pose, float* sink, void* stream) {
   if (!b || !pose || !sink) return FC_ERR_NULL;

@@ -219,6 +219,26 @@ hipError_t launch_query_chunked(const BwdArgs& a, const QueryExtra& q, const Fwd
 // measurement aid: k_query_backward's items, loop and corner loads, no arithmetic
 hipError_t launch_gather_probe(const BwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// Patch reduction (Algorithm 1): one workgroup per environment, batches of
+// kPatchBatch vertices, at most kPatchMax patches.
+constexpr int kPatchBlock = 256;
+constexpr int kPatchVpt = 4;
+constexpr int kPatchBatch = kPatchBlock * kPatchVpt;  // 1024, the paper's batch
+constexpr int kPatchMax = 256;
+struct PatchArgs {
+  int n_max;       // N, 1 <= N <= kPatchMax
+  float cos_sim;   // similar(a, b): dot(a, b) >= cos_sim
+  int* count;      // [n_env] patches kept
+  int* founder;    // [n_env * N] founding vertex, -1 if the slot is empty
+  float* normal;   // [3][n_env * N] the patch normal (the founder's)
+  int* vidx;       // [n_env * N] deepest member, -1 if empty
+  float* depth;    // [n_env * N] its depth
+  float* point;    // [3][n_env * N] its x_B
+  int* members;    // [n_env * N]
+};
+hipError_t launch_patches(const FwdArgs& a, const PatchArgs& p, int dtype, int layout, hipStream_t s,
+                          const KernelMarks* m);
+
 // Sparse conversion: flags[b] = 1 if brick b is stored (a node with
 // |value| <= band, nodes of both signs, or nodes past the grid's edge).
 hipError_t launch_sparse_classify(const void* src, int dtype, int nx, int ny, int nz, int bx, int by, int bz,

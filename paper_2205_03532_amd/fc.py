@@ -17,7 +17,8 @@ import os
 
 import numpy as np
 
-FC_KERNEL_FORWARD, FC_KERNEL_BACKWARD, FC_KERNEL_QUERY_BACKWARD, FC_KERNEL_GATHER_PROBE, FC_KERNEL_FACES = range(5)
+(FC_KERNEL_FORWARD, FC_KERNEL_BACKWARD, FC_KERNEL_QUERY_BACKWARD, FC_KERNEL_GATHER_PROBE, FC_KERNEL_FACES,
+ FC_KERNEL_PATCHES) = range(6)
 
 # the in-tree build; FC_LIB_PATH selects another build of the same sources
 LIB_PATH = os.environ.get("FC_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -54,6 +55,19 @@ class fc_candidates(C.Structure):
 
 class fc_pgd(C.Structure):
     _fields_ = [("iters", C.c_int32), ("step0", C.c_float)]
+
+
+class fc_patch_params(C.Structure):
+    _fields_ = [("max_patches", C.c_int32), ("cos_sim", C.c_float)]
+
+
+class fc_patches(C.Structure):
+    _fields_ = [("count", C.c_void_p), ("founder", C.c_void_p), ("normal", C.c_void_p), ("vidx", C.c_void_p),
+                ("depth", C.c_void_p), ("point", C.c_void_p), ("members", C.c_void_p)]
+
+
+PATCH_MAX = 128  # N (the paper: 128 <= N <= 256)
+PATCH_COS = float(np.float32(np.cos(np.radians(10.0))))  # similar normals: within 10 degrees
 
 
 class fc_contacts(C.Structure):
@@ -103,6 +117,8 @@ SIGNATURES = {
     "fc_sdf_query_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_pgd), C.POINTER(fc_candidates),
                                      C.POINTER(fc_contacts), C.c_void_p, C.c_size_t, C.c_void_p]),
     "fc_batch_face_queries": (C.c_int64, [C.c_void_p]),
+    "fc_contact_patches": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_patch_params), C.POINTER(fc_patches),
+                                     C.c_void_p]),
     "fc_grid_sparse_bytes": (C.c_int, [C.POINTER(fc_grid), C.c_float, C.POINTER(C.c_size_t), C.c_void_p]),
     "fc_grid_to_sparse": (C.c_int, [C.POINTER(fc_grid), C.c_float, C.c_void_p, C.c_size_t, C.POINTER(fc_grid),
                                     C.c_void_p]),
@@ -287,6 +303,17 @@ class Batch:
                     bin=torch.empty(Q, dtype=torch.int16, device=self.device),
                     point=torch.empty(3, Q, dtype=torch.float32, device=self.device))
 
+    def new_patches(self, max_patches=PATCH_MAX):
+        """Outputs of fc_contact_patches: slot e * N + p."""
+        import torch
+
+        S = self.n_env * max_patches
+        i32 = dict(dtype=torch.int32, device=self.device)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        return dict(count=torch.empty(self.n_env, **i32), founder=torch.empty(S, **i32),
+                    normal=torch.empty(3, S, **f32), vidx=torch.empty(S, **i32), depth=torch.empty(S, **f32),
+                    point=torch.empty(3, S, **f32), members=torch.empty(S, **i32))
+
     def new_contacts(self):
         import torch
 
@@ -396,6 +423,15 @@ def fc_sdf_query_faces(batch: Batch, pose, cand=None, fused_out=None, iters=PGD_
     _check(lib().fc_sdf_query_faces(batch.handle, _ptr(pose), C.byref(p), _byref(cs), _byref(os_),
                                     C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes, _stream(stream)),
            "fc_sdf_query_faces")
+
+
+def fc_contact_patches(batch: Batch, pose, out, max_patches=PATCH_MAX, cos_sim=PATCH_COS, stream=None):
+    """Patch reduction (Algorithm 1) of every environment into ``out``
+    (Batch.new_patches(max_patches))."""
+    prm = fc_patch_params(int(max_patches), float(cos_sim))
+    ps = fc_patches(*[_ptr(out[k]) for k in ("count", "founder", "normal", "vidx", "depth", "point", "members")])
+    _check(lib().fc_contact_patches(batch.handle, _ptr(pose), C.byref(prm), C.byref(ps), _stream(stream)),
+           "fc_contact_patches")
 
 
 def fc_gather_probe(batch: Batch, pose, sink, stream=None):

@@ -128,6 +128,24 @@ def test_brick_size_query(L):
     assert L.fc_grid_brick_bytes(C.byref(g), 1) == 0
 
 
+def test_contact_patches_rejects_invalid_arguments(L):
+    """Checked before anything touches the batch: no HIP call here."""
+    fake = C.c_void_p(FAKE)
+    ok = fc.fc_patch_params(128, 0.98)
+    outs = fc.fc_patches(*([fake] * 7))
+    call = L.fc_contact_patches
+    assert call(None, fake, C.byref(ok), C.byref(outs), None) == fc.FC_ERR_NULL
+    assert call(fake, None, C.byref(ok), C.byref(outs), None) == fc.FC_ERR_NULL
+    assert call(fake, fake, None, C.byref(outs), None) == fc.FC_ERR_NULL
+    assert call(fake, fake, C.byref(ok), None, None) == fc.FC_ERR_NULL
+    for i in range(7):
+        ptrs = [fake] * 7
+        ptrs[i] = None
+        assert call(fake, fake, C.byref(ok), C.byref(fc.fc_patches(*ptrs)), None) == fc.FC_ERR_NULL
+    for n, cs in ((0, 0.9), (257, 0.9), (128, float("nan")), (128, float("inf"))):
+        assert call(fake, fake, C.byref(fc.fc_patch_params(n, cs)), C.byref(outs), None) == fc.FC_ERR_RANGE
+
+
 def test_sparse_conversion_rejects_invalid_arguments(L):
     """Every check happens before the classification kernel: no HIP call here."""
     g = fc.fc_grid(C.c_void_p(FAKE), 0, 0, 64, 64, 64, (C.c_float * 3)(0, 0, 0), 1e-3)
