@@ -46,7 +46,8 @@ TUNE_CACHE = os.path.join(ROOT, "paper_2205_03532_amd", "autotune.json")
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "paper_2205_03532_amd", "traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2205_03532_amd", "csrc", f) for f in ("fc_kernels.hip", "fc_internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2205_03532_amd", "csrc", f)
+                  for f in ("fc_kernels.hip", "fc_device.h", "fc_internal.h")]
 COPY_PROBE_BYTES = 256 << 20
 
 

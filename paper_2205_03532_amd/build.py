@@ -55,7 +55,7 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ("fc_kernels.hip", "fc_bake.hip"):
+    for src in ("fc_kernels.hip", "fc_patches.hip", "fc_bake.hip"):
         objs.append(os.path.join(BUILD, src.replace(".hip", ".o")))
         _run([hipcc, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", objs[-1]], verbose)
     objs.append(os.path.join(BUILD, "fc_api.o"))

@@ -24,320 +24,11 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
-#include "fc_internal.h"
+#include "fc_device.h"
 
 namespace fcimpl {
 namespace {
 
-constexpr int kF32 = FC_F32, kF16 = FC_F16, kBF16 = FC_BF16;
-
-// ---------------------------------------------------------------------------
-// rigid transform (quaternion x,y,z,w -> R = I + 2w[v]x + 2[v]x^2, no renormalisation)
-// ---------------------------------------------------------------------------
-struct Rigid {
-  float r00, r01, r02, r10, r11, r12, r20, r21, r22, tx, ty, tz;
-};
-
-__device__ __forceinline__ Rigid load_pose(const float* __restrict__ pose, int n_env, int e) {
-  const float qx = pose[e], qy = pose[n_env + e], qz = pose[2 * n_env + e], qw = pose[3 * n_env + e];
-  const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
-  const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
-  const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
-  Rigid r;
-  r.r00 = 1.f - 2.f * (yy + zz);
-  r.r01 = 2.f * (xy - wz);
-  r.r02 = 2.f * (xz + wy);
-  r.r10 = 2.f * (xy + wz);
-  r.r11 = 1.f - 2.f * (xx + zz);
-  r.r12 = 2.f * (yz - wx);
-  r.r20 = 2.f * (xz - wy);
-  r.r21 = 2.f * (yz + wx);
-  r.r22 = 1.f - 2.f * (xx + yy);
-  r.tx = pose[4 * n_env + e];
-  r.ty = pose[5 * n_env + e];
-  r.tz = pose[6 * n_env + e];
-  return r;
-}
-
-__device__ __forceinline__ void transform(const Rigid& P, float x, float y, float z, float& ox, float& oy,
-                                          float& oz) {
-  ox = fmaf(P.r00, x, fmaf(P.r01, y, fmaf(P.r02, z, P.tx)));
-  oy = fmaf(P.r10, x, fmaf(P.r11, y, fmaf(P.r12, z, P.ty)));
-  oz = fmaf(P.r20, x, fmaf(P.r21, y, fmaf(P.r22, z, P.tz)));
-}
-
-// ---------------------------------------------------------------------------
-// grid access
-// ---------------------------------------------------------------------------
-struct Cell {
-  int ix, iy, iz;
-  float tx, ty, tz;
-  bool inside;
-};
-
-// Grid coordinate u = (x - origin)/h; inside iff 0 <= u <= n-1 on every axis;
-// cell = min(floor(u), n-2); t = u - cell.
-__device__ __forceinline__ Cell locate(const GridDev& g, float x, float y, float z) {
-  float ux = (x - g.ox) * g.inv_h;
-  float uy = (y - g.oy) * g.inv_h;
-  float uz = (z - g.oz) * g.inv_h;
-  Cell c;
-  c.inside = (ux >= 0.f) & (ux <= (float)(g.nx - 1)) & (uy >= 0.f) & (uy <= (float)(g.ny - 1)) & (uz >= 0.f) &
-             (uz <= (float)(g.nz - 1));
-  if (!c.inside) ux = uy = uz = 0.f;  // also clears NaN: the gather stays in bounds
-  c.ix = min((int)floorf(ux), g.nx - 2);
-  c.iy = min((int)floorf(uy), g.ny - 2);
-  c.iz = min((int)floorf(uz), g.nz - 2);
-  c.tx = ux - (float)c.ix;
-  c.ty = uy - (float)c.iy;
-  c.tz = uz - (float)c.iz;
-  return c;
-}
-
-// (v[0], v[1]) at p as one unaligned 8-byte (FP32) or 4-byte (FP16/BF16) load
-template <int DT>
-__device__ __forceinline__ float2 ld_pair(const void* __restrict__ p);
-
-template <>
-__device__ __forceinline__ float2 ld_pair<kF32>(const void* __restrict__ p) {
-  float2 r;
-  __builtin_memcpy(&r, p, 8);
-  return r;
-}
-template <>
-__device__ __forceinline__ float2 ld_pair<kF16>(const void* __restrict__ p) {
-  unsigned u;
-  __builtin_memcpy(&u, p, 4);
-  return make_float2(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))),
-                     __half2float(__ushort_as_half((unsigned short)(u >> 16))));
-}
-template <>
-__device__ __forceinline__ float2 ld_pair<kBF16>(const void* __restrict__ p) {
-  unsigned u;
-  __builtin_memcpy(&u, p, 4);
-  return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
-}
-
-// Sparse grid, brick not stored: the fine cell (lx, ly, lz) of the brick's
-// 3x3x3 cells takes the values at its corners of the trilinear interpolant of
-// the brick's 8 corner nodes (the coarse grid).  Trilinear interpolation
-// reproduces a trilinear function exactly, so the cell's interpolant is the
-// coarse one (up to FP32 rounding), value and gradient.
-template <int DT>
-__device__ __forceinline__ void coarse_corners(const GridDev& g, unsigned bxi, unsigned byi, unsigned bzi,
-                                               unsigned lx, unsigned ly, unsigned lz, float c[8]) {
-  constexpr size_t E = DT == kF32 ? 4 : 2;
-  const unsigned cx = (unsigned)g.bx + 1, cxy = cx * ((unsigned)g.by + 1);
-  const char* b = static_cast<const char*>(g.coarse) + (size_t)((bzi * ((unsigned)g.by + 1) + byi) * cx + bxi) * E;
-  const float2 e00 = ld_pair<DT>(b);                        // y0 z0
-  const float2 e10 = ld_pair<DT>(b + (size_t)cx * E);        // y1 z0
-  const float2 e01 = ld_pair<DT>(b + (size_t)cxy * E);       // y0 z1
-  const float2 e11 = ld_pair<DT>(b + (size_t)(cxy + cx) * E);  // y1 z1
-  const auto third = [](unsigned k) { return k == 3u ? 1.f : (float)k * (1.f / 3.f); };  // k / 3
-  const float fx0 = third(lx), fx1 = third(lx + 1);
-  const float fy0 = third(ly), fy1 = third(ly + 1);
-  const float fz0 = third(lz), fz1 = third(lz + 1);
-  // along x: a[sx][y + 2z]
-  const float d00 = e00.y - e00.x, d10 = e10.y - e10.x, d01 = e01.y - e01.x, d11 = e11.y - e11.x;
-  const float a0[4] = {fmaf(fx0, d00, e00.x), fmaf(fx0, d10, e10.x), fmaf(fx0, d01, e01.x), fmaf(fx0, d11, e11.x)};
-  const float a1[4] = {fmaf(fx1, d00, e00.x), fmaf(fx1, d10, e10.x), fmaf(fx1, d01, e01.x), fmaf(fx1, d11, e11.x)};
-  // along y, then z
-#pragma unroll
-  for (int sx = 0; sx < 2; ++sx) {
-    const float* a = sx ? a1 : a0;
-    const float dy_z0 = a[1] - a[0], dy_z1 = a[3] - a[2];
-    const float b00 = fmaf(fy0, dy_z0, a[0]), b10 = fmaf(fy1, dy_z0, a[0]);  // z0: y0, y1
-    const float b01 = fmaf(fy0, dy_z1, a[2]), b11 = fmaf(fy1, dy_z1, a[2]);  // z1: y0, y1
-    const float u0 = b01 - b00, u1 = b11 - b10;                              // along z at y0, y1
-    c[sx + 0] = fmaf(fz0, u0, b00);
-    c[sx + 2] = fmaf(fz0, u1, b10);
-    c[sx + 4] = fmaf(fz1, u0, b00);
-    c[sx + 6] = fmaf(fz1, u1, b10);
-  }
-}
-
-// Corner order: c[a + 2b + 4c] = value at node (ix+a, iy+b, iz+c).
-template <int DT, int LAYOUT>
-__device__ __forceinline__ void gather(const GridDev& g, const Cell& cl, float c[8]) {
-  // cell indexes are >= 0 and element indexes < 2^31 (checked at batch
-  // creation): unsigned arithmetic, so the divisions need no sign fix-up
-  unsigned i0, sy, sz;
-  const unsigned ix = (unsigned)cl.ix, iy = (unsigned)cl.iy, iz = (unsigned)cl.iz;
-  if constexpr (LAYOUT == FC_LAYOUT_LINEAR) {
-    sy = (unsigned)g.nx;
-    sz = (unsigned)g.nx * (unsigned)g.ny;
-    i0 = (iz * (unsigned)g.ny + iy) * (unsigned)g.nx + ix;
-  } else if constexpr (LAYOUT == FC_LAYOUT_SPARSE) {
-    const unsigned bxi = ix / 3u, byi = iy / 3u, bzi = iz / 3u;
-    const unsigned lx = ix - 3u * bxi, ly = iy - 3u * byi, lz = iz - 3u * bzi;
-    const int slot = g.map[(bzi * (unsigned)g.by + byi) * (unsigned)g.bx + bxi];
-    if (slot < 0) {
-      coarse_corners<DT>(g, bxi, byi, bzi, lx, ly, lz, c);
-      return;
-    }
-    sy = 4;
-    sz = 16;
-    i0 = (unsigned)slot * 64u + (lz * 16u + ly * 4u + lx);
-  } else {
-    using B = BrickShape<LAYOUT>;
-    constexpr unsigned CX = B::NX - 1, CY = B::NY - 1, CZ = B::NZ - 1;
-    const unsigned bxi = ix / CX, byi = iy / CY, bzi = iz / CZ;
-    const unsigned lx = ix - CX * bxi, ly = iy - CY * byi, lz = iz - CZ * bzi;
-    sy = B::NX;
-    sz = B::NX * B::NY;
-    i0 = ((bzi * (unsigned)g.by + byi) * (unsigned)g.bx + bxi) * (B::NX * B::NY * B::NZ) + (lz * sz + ly * sy + lx);
-  }
-  // one 64-bit base per query; the other rows at constant offsets (bricks)
-  constexpr size_t E = DT == kF32 ? 4 : 2;
-  const char* b = static_cast<const char*>(g.data) + (size_t)i0 * E;
-  const float2 p00 = ld_pair<DT>(b);
-  const float2 p10 = ld_pair<DT>(b + (size_t)sy * E);
-  const float2 p01 = ld_pair<DT>(b + (size_t)sz * E);
-  const float2 p11 = ld_pair<DT>(b + (size_t)(sz + sy) * E);
-  c[0] = p00.x; c[1] = p00.y;
-  c[2] = p10.x; c[3] = p10.y;
-  c[4] = p01.x; c[5] = p01.y;
-  c[6] = p11.x; c[7] = p11.y;
-}
-
-// Trilinear value and its exact gradient in grid units (multiply by 1/h for
-// metres): phi = sum W_a(tx) W_b(ty) W_c(tz) C_abc, evaluated as nested lerps.
-__device__ __forceinline__ void trilinear(const float c[8], float tx, float ty, float tz, float& phi, float& gx,
-                                          float& gy, float& gz) {
-  const float dx00 = c[1] - c[0], dx10 = c[3] - c[2], dx01 = c[5] - c[4], dx11 = c[7] - c[6];
-  const float a00 = fmaf(tx, dx00, c[0]);
-  const float a10 = fmaf(tx, dx10, c[2]);
-  const float a01 = fmaf(tx, dx01, c[4]);
-  const float a11 = fmaf(tx, dx11, c[6]);
-  const float dy0 = a10 - a00, dy1 = a11 - a01;
-  const float b0 = fmaf(ty, dy0, a00);
-  const float b1 = fmaf(ty, dy1, a01);
-  const float dz = b1 - b0;
-  phi = fmaf(tz, dz, b0);
-  gz = dz;
-  gy = fmaf(tz, dy1 - dy0, dy0);
-  const float e0 = fmaf(ty, dx10 - dx00, dx00);
-  const float e1 = fmaf(ty, dx11 - dx01, dx01);
-  gx = fmaf(tz, e1 - e0, e0);
-}
-
-template <int DT, int LAYOUT>
-__device__ __forceinline__ void sample(const GridDev& g, float x, float y, float z, float& phi, float& gx, float& gy,
-                                       float& gz, bool& inside) {
-  const Cell cl = locate(g, x, y, z);
-  float c[8];
-  gather<DT, LAYOUT>(g, cl, c);
-  trilinear(c, cl.tx, cl.ty, cl.tz, phi, gx, gy, gz);
-  inside = cl.inside;
-}
-
-__device__ __forceinline__ void normalize(float gx, float gy, float gz, float& nx, float& ny, float& nz) {
-  const float l2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
-  if (l2 > 0.f) {
-    const float r = rsqrtf(l2);
-    nx = gx * r;
-    ny = gy * r;
-    nz = gz * r;
-  } else {
-    nx = ny = nz = 0.f;
-  }
-}
-
-// lowest k maximising n . d_k
-__device__ __forceinline__ int argmax_bin(const float* __restrict__ dirs, int K, float nx, float ny, float nz) {
-  float best = fmaf(nz, dirs[2 * K], fmaf(ny, dirs[K], nx * dirs[0]));
-  int bin = 0;
-  for (int k = 1; k < K; ++k) {
-    const float d = fmaf(nz, dirs[2 * K + k], fmaf(ny, dirs[K + k], nx * dirs[k]));
-    if (d > best) {
-      best = d;
-      bin = k;
-    }
-  }
-  return bin;
-}
-
-// Cube-map cell of a nonzero normal (see BinCell): the dominant axis picks the
-// face, the other two components divided by it give (u, v) in [-1, 1].
-__device__ __forceinline__ int cube_cell(float nx, float ny, float nz) {
-  const float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
-  int face;
-  float u, v, m;
-  if ((ax >= ay) & (ax >= az)) {
-    face = nx >= 0.f ? 0 : 1;
-    u = ny;
-    v = nz;
-    m = ax;
-  } else if (ay >= az) {
-    face = ny >= 0.f ? 2 : 3;
-    u = nx;
-    v = nz;
-    m = ay;
-  } else {
-    face = nz >= 0.f ? 4 : 5;
-    u = nx;
-    v = ny;
-    m = az;
-  }
-  // hardware reciprocal (1 ulp): the table's cones carry a 1e-4 rad margin
-  // for the cell choice, far above this rounding
-  const float s = (0.5f * kLutN) * __builtin_amdgcn_rcpf(m);
-  const int iu = min(max((int)floorf(fmaf(u, s, 0.5f * kLutN)), 0), kLutN - 1);
-  const int iv = min(max((int)floorf(fmaf(v, s, 0.5f * kLutN)), 0), kLutN - 1);
-  return (face * kLutN + iv) * kLutN + iu;
-}
-
-// The same argmax as argmax_bin (same dot products, same lowest-k tie rule),
-// evaluated only over the bins the normal's cube-map cell lists.  The table
-// is built so that every bin that can reach the maximum for a normal in the
-// cell is listed, so the result is identical.
-__device__ __forceinline__ int argmax_bin_lut(const BinCell* __restrict__ lut, const float4* __restrict__ dir4,
-                                              const float* __restrict__ dirs, int K, float nx, float ny,
-                                              float nz) {
-  if ((nx == 0.f) & (ny == 0.f) & (nz == 0.f)) return 0;
-  // the cell's 16 bytes (n, k[0..14]) in four registers; the loop is unrolled
-  // so every byte index is a constant (no private-array indexing)
-  const uint4 cw = *reinterpret_cast<const uint4*>(&lut[cube_cell(nx, ny, nz)]);
-  const unsigned w[4] = {cw.x, cw.y, cw.z, cw.w};
-  const int n = (int)(w[0] & 0xffu);
-  if (n == kLutFull) return argmax_bin(dirs, K, nx, ny, nz);
-  int bin = (int)((w[0] >> 8) & 0xffu);
-  float4 d = dir4[bin];
-  float best = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
-#pragma unroll
-  for (int i = 1; i < kLutMax; ++i) {
-    if (i < n) {
-      const int b = i + 1;  // byte of k[i]
-      const int k = (int)((w[b >> 2] >> ((b & 3) * 8)) & 0xffu);
-      d = dir4[k];
-      const float v = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
-      if (v > best) {
-        best = v;
-        bin = k;
-      }
-    }
-  }
-  return bin;
-}
-
-// ---------------------------------------------------------------------------
-// reduction keys: (sortable depth << 32) | (0xFFFFFFFF - vidx); max = deepest,
-// then lowest index.  -0.0 is folded to +0.0; key 0 means "empty".
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long make_key(float depth, unsigned vidx) {
-  if (depth == 0.f) depth = 0.f;
-  unsigned u = __float_as_uint(depth);
-  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-  return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - vidx);
-}
-
-__device__ __forceinline__ float key_depth(unsigned long long key) {
-  unsigned u = (unsigned)(key >> 32);
-  u = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
-  return __uint_as_float(u);
-}
-
-__device__ __forceinline__ unsigned key_vidx(unsigned long long key) { return 0xFFFFFFFFu - (unsigned)key; }
 
 // ---------------------------------------------------------------------------
 // DPP lane permutations (register to register) for the adjoint's wavefront
@@ -848,237 +539,6 @@ __global__ __launch_bounds__(256) void k_face_payload(FwdArgs A) {
   }
   const unsigned long long nonempty = __ballot(have);
   if (lane == 0) A.o_count[e] = __popcll(nonempty);
-}
-
-// ---------------------------------------------------------------------------
-// patch reduction (Algorithm 1)
-// ---------------------------------------------------------------------------
-// FP32 dot without fused multiply-adds: (a.x b.x + a.y b.y) + a.z b.z (the
-// file is compiled with -ffp-contract=off).
-__device__ __forceinline__ float dot3_nofma(float ax, float ay, float az, float bx, float by, float bz) {
-  return (ax * bx + ay * by) + az * bz;
-}
-
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long w = __shfl_xor(v, o);
-    v = w > v ? w : v;
-  }
-  return v;
-}
-
-__device__ __forceinline__ int wave_sum_i32(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-// (d, p) with the largest d, the lowest p on ties
-__device__ __forceinline__ void wave_argmax(float& d, int& p) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const float d2 = __shfl_xor(d, o);
-    const int p2 = __shfl_xor(p, o);
-    if (d2 > d || (d2 == d && p2 < p)) {
-      d = d2;
-      p = p2;
-    }
-  }
-}
-
-// One workgroup per environment.  For each batch of 1024 vertices: Generate
-// the candidates (the vertex query's values, bit for bit), Assign each to the
-// most similar patch that existed when the batch began, then repeat
-// FindDeepest / BinReduce / AddPatch until no candidate remains.  Patches live
-// in LDS; member counts and deepest keys are order-independent atomics.
-template <int DT, int LAYOUT>
-__global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P) {
-  __shared__ float s_pn[kPatchMax][3];
-  __shared__ unsigned long long s_pkey[kPatchMax];
-  __shared__ int s_pmem[kPatchMax];
-  __shared__ int s_pfound[kPatchMax];
-  __shared__ unsigned long long s_wkey[kPatchBlock / 64];
-  __shared__ int s_wint[kPatchBlock / 64];
-  __shared__ float s_wd[kPatchBlock / 64];
-  __shared__ float s_bn[3];
-  __shared__ int s_np;
-
-  const int e = blockIdx.x;
-  const int gm = A.envs[e].gm;
-  const GridDev& g = A.grids[gm & 0xff];
-  const MeshDev& m = A.meshes[gm >> 8];
-  const Rigid R = load_pose(A.pose, A.n_env, e);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const float cs = P.cos_sim;
-  if (tid == 0) s_np = 0;
-  __syncthreads();
-
-  for (int b0 = 0; b0 < m.n; b0 += kPatchBatch) {
-    // Generate
-    unsigned long long key[kPatchVpt];
-    float nx[kPatchVpt], ny[kPatchVpt], nz[kPatchVpt];
-    bool live[kPatchVpt];
-    {
-      float px[kPatchVpt], py[kPatchVpt], pz[kPatchVpt];
-      bool ok[kPatchVpt];
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j) {
-        const int v = b0 + j * kPatchBlock + tid;
-        ok[j] = v < m.n;
-        float x = 0.f, y = 0.f, z = 0.f;
-        if (ok[j]) {
-          x = m.x[v];
-          y = m.y[v];
-          z = m.z[v];
-        }
-        transform(R, x, y, z, px[j], py[j], pz[j]);
-      }
-      Cell cl[kPatchVpt];
-      float c[kPatchVpt][8];
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j) cl[j] = locate(g, px[j], py[j], pz[j]);
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j) gather<DT, LAYOUT>(g, cl[j], c[j]);
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j) {
-        float phi, gx, gy, gz;
-        trilinear(c[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
-        live[j] = ok[j] & cl[j].inside & (phi < A.margin);
-        nx[j] = ny[j] = nz[j] = 0.f;
-        key[j] = 0ull;
-        if (live[j]) {
-          normalize(gx, gy, gz, nx[j], ny[j], nz[j]);
-          key[j] = make_key(-phi, (unsigned)(b0 + j * kPatchBlock + tid));
-        }
-      }
-    }
-    // Assign, against the patches present as the batch begins
-    const int np0 = s_np;
-#pragma unroll
-    for (int j = 0; j < kPatchVpt; ++j) {
-      if (!live[j]) continue;
-      int best = -1;
-      float bd = 0.f;
-      for (int p = 0; p < np0; ++p) {
-        const float d = dot3_nofma(nx[j], ny[j], nz[j], s_pn[p][0], s_pn[p][1], s_pn[p][2]);
-        if (d >= cs && (best < 0 || d > bd)) {
-          best = p;
-          bd = d;
-        }
-      }
-      if (best >= 0) {
-        atomicAdd(&s_pmem[best], 1);
-        atomicMax(&s_pkey[best], key[j]);
-        live[j] = false;
-      }
-    }
-    __syncthreads();
-    // FindDeepest / BinReduce / AddPatch while candidates remain
-    for (;;) {
-      unsigned long long mk = 0ull;
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j)
-        if (live[j] && key[j] > mk) mk = key[j];
-      mk = wave_max_u64(mk);
-      if (lane == 0) s_wkey[wave] = mk;
-      __syncthreads();
-      unsigned long long best = s_wkey[0];
-#pragma unroll
-      for (int w = 1; w < kPatchBlock / 64; ++w) best = s_wkey[w] > best ? s_wkey[w] : best;
-      if (best == 0ull) break;  // the same value in every thread
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j)
-        if (live[j] && key[j] == best) {  // keys are unique: one owner
-          s_bn[0] = nx[j];
-          s_bn[1] = ny[j];
-          s_bn[2] = nz[j];
-        }
-      __syncthreads();  // s_bn written; every thread has read s_wkey
-      const float bx = s_bn[0], by = s_bn[1], bz = s_bn[2];
-      int cnt = 0;
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j)
-        if (live[j] && (key[j] == best || dot3_nofma(bx, by, bz, nx[j], ny[j], nz[j]) >= cs)) {
-          ++cnt;
-          live[j] = false;
-        }
-      cnt = wave_sum_i32(cnt);
-      // the most similar existing patch (needed only when the list is full)
-      const int np = s_np;
-      float d = -__builtin_inff();
-      int pj = 0x7fffffff;
-      if (np >= P.n_max && tid < np) {
-        d = dot3_nofma(bx, by, bz, s_pn[tid][0], s_pn[tid][1], s_pn[tid][2]);
-        pj = tid;
-      }
-      wave_argmax(d, pj);
-      if (lane == 0) {
-        s_wint[wave] = cnt;
-        s_wd[wave] = d;
-        s_wkey[wave] = (unsigned long long)(unsigned)pj;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        int members = 0;
-        float dd = -__builtin_inff();
-        int jj = 0x7fffffff;
-        for (int w = 0; w < kPatchBlock / 64; ++w) {
-          members += s_wint[w];
-          const int pw = (int)s_wkey[w];
-          if (s_wd[w] > dd || (s_wd[w] == dd && pw < jj)) {
-            dd = s_wd[w];
-            jj = pw;
-          }
-        }
-        int slot = -1;
-        if (np < P.n_max) {
-          slot = np;
-          s_np = np + 1;
-        } else if ((float)members * key_depth(best) > (float)s_pmem[jj] * key_depth(s_pkey[jj])) {
-          slot = jj;
-        }
-        if (slot >= 0) {
-          s_pn[slot][0] = bx;
-          s_pn[slot][1] = by;
-          s_pn[slot][2] = bz;
-          s_pkey[slot] = best;
-          s_pmem[slot] = members;
-          s_pfound[slot] = (int)key_vidx(best);
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // the patch list, each with its deepest member's record
-  const int np = s_np;
-  if (tid == 0) P.count[e] = np;
-  const long long S = (long long)A.n_env * P.n_max;
-  for (int p = tid; p < P.n_max; p += kPatchBlock) {
-    const long long s = (long long)e * P.n_max + p;
-    if (p < np) {
-      const unsigned v = key_vidx(s_pkey[p]);
-      float xb, yb, zb;
-      transform(R, m.x[v], m.y[v], m.z[v], xb, yb, zb);
-      P.founder[s] = s_pfound[p];
-      P.vidx[s] = (int)v;
-      P.depth[s] = key_depth(s_pkey[p]);
-      P.members[s] = s_pmem[p];
-      P.normal[s] = s_pn[p][0];
-      P.normal[S + s] = s_pn[p][1];
-      P.normal[2 * S + s] = s_pn[p][2];
-      P.point[s] = xb;
-      P.point[S + s] = yb;
-      P.point[2 * S + s] = zb;
-    } else {
-      P.founder[s] = -1;
-      P.vidx[s] = -1;
-      P.depth[s] = 0.f;
-      P.members[s] = 0;
-      P.normal[s] = P.normal[S + s] = P.normal[2 * S + s] = 0.f;
-      P.point[s] = P.point[S + s] = P.point[2 * S + s] = 0.f;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1616,20 +1076,6 @@ __global__ void k_sparse_fill(const T* __restrict__ src, int nx, int ny, int nz,
   }
 }
 
-// Optional HIP events around the main kernel of the launch in progress (set
-// by the launch_* entry points for the calling thread; see KernelMarks).
-thread_local const KernelMarks* t_marks = nullptr;
-
-struct MarksScope {
-  explicit MarksScope(const KernelMarks* m) { t_marks = m; }
-  ~MarksScope() { t_marks = nullptr; }
-};
-
-hipError_t mark(bool after, hipStream_t s) {
-  if (!t_marks) return hipSuccess;
-  return hipEventRecord(after ? static_cast<hipEvent_t>(t_marks->after) : static_cast<hipEvent_t>(t_marks->before),
-                        s);
-}
 
 template <int DT, int LAYOUT, int BLOCK, int VPT>
 hipError_t fwd_launch(const FwdArgs& a, int persistent, int xcd, int grid, bool from_cand, hipStream_t s) {
@@ -1907,36 +1353,6 @@ hipError_t launch_faces(const FwdArgs& a, int dtype, int layout, hipStream_t s, 
     case kF32: return faces_layout<kF32>(a, layout, s);
     case kF16: return faces_layout<kF16>(a, layout, s);
     case kBF16: return faces_layout<kBF16>(a, layout, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int DT, int LAYOUT>
-hipError_t patches_launch(const FwdArgs& a, const PatchArgs& p, hipStream_t s) {
-  hipError_t e = mark(false, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_patches<DT, LAYOUT>), dim3(a.n_env), dim3(kPatchBlock), 0, s, a, p);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return mark(true, s);
-}
-
-template <int DT>
-hipError_t patches_layout(const FwdArgs& a, const PatchArgs& p, int layout, hipStream_t s) {
-  if (layout == FC_LAYOUT_BRICK) return patches_launch<DT, FC_LAYOUT_BRICK>(a, p, s);
-  if (layout == FC_LAYOUT_SLAB) return patches_launch<DT, FC_LAYOUT_SLAB>(a, p, s);
-  if (layout == FC_LAYOUT_SPARSE) return patches_launch<DT, FC_LAYOUT_SPARSE>(a, p, s);
-  return patches_launch<DT, FC_LAYOUT_LINEAR>(a, p, s);
-}
-
-hipError_t launch_patches(const FwdArgs& a, const PatchArgs& p, int dtype, int layout, hipStream_t s,
-                          const KernelMarks* m) {
-  if (a.n_env <= 0) return hipSuccess;
-  const MarksScope scope(m);
-  switch (dtype) {
-    case kF32: return patches_layout<kF32>(a, p, layout, s);
-    case kF16: return patches_layout<kF16>(a, p, layout, s);
-    case kBF16: return patches_layout<kBF16>(a, p, layout, s);
   }
   return hipErrorInvalidValue;
 }

@@ -1,0 +1,278 @@
+// HIP kernel for gfx950 (CDNA4): the patch-based contact reduction of
+// Narang et al. (Factory, RSS 2022), Section III-C, Algorithm 1: per shape
+// pair, for each batch of 1024 features, Generate candidates, Assign them to
+// existing patches by normal similarity, then FindDeepest / BinReduce /
+// AddPatch until none remain -- in LDS, as the paper does in shared memory.
+//
+// Numerics: compiled with -ffp-contract=off; the candidates are the vertex
+// queries of fc_device.h, bit for bit; the similarity dot has no fused
+// multiply-add, so a CPU evaluation in FP32 takes the same decisions.
+#include "fc_device.h"
+
+namespace fcimpl {
+namespace {
+
+// ---------------------------------------------------------------------------
+// patch reduction (Algorithm 1)
+// ---------------------------------------------------------------------------
+// FP32 dot without fused multiply-adds: (a.x b.x + a.y b.y) + a.z b.z (the
+// file is compiled with -ffp-contract=off).
+__device__ __forceinline__ float dot3_nofma(float ax, float ay, float az, float bx, float by, float bz) {
+  return (ax * bx + ay * by) + az * bz;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// (d, p) with the largest d, the lowest p on ties
+__device__ __forceinline__ void wave_argmax(float& d, int& p) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const float d2 = __shfl_xor(d, o);
+    const int p2 = __shfl_xor(p, o);
+    if (d2 > d || (d2 == d && p2 < p)) {
+      d = d2;
+      p = p2;
+    }
+  }
+}
+
+// One workgroup per environment.  For each batch of 1024 vertices: Generate
+// the candidates (the vertex query's values, bit for bit), Assign each to the
+// most similar patch that existed when the batch began, then repeat
+// FindDeepest / BinReduce / AddPatch until no candidate remains.  Patches live
+// in LDS; member counts and deepest keys are order-independent atomics.
+template <int DT, int LAYOUT>
+__global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P) {
+  __shared__ float s_pn[kPatchMax][3];
+  __shared__ unsigned long long s_pkey[kPatchMax];
+  __shared__ int s_pmem[kPatchMax];
+  __shared__ int s_pfound[kPatchMax];
+  __shared__ unsigned long long s_wkey[kPatchBlock / 64];
+  __shared__ int s_wint[kPatchBlock / 64];
+  __shared__ float s_wd[kPatchBlock / 64];
+  __shared__ float s_bn[3];
+  __shared__ int s_np;
+
+  const int e = blockIdx.x;
+  const int gm = A.envs[e].gm;
+  const GridDev& g = A.grids[gm & 0xff];
+  const MeshDev& m = A.meshes[gm >> 8];
+  const Rigid R = load_pose(A.pose, A.n_env, e);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const float cs = P.cos_sim;
+  if (tid == 0) s_np = 0;
+  __syncthreads();
+
+  for (int b0 = 0; b0 < m.n; b0 += kPatchBatch) {
+    // Generate
+    unsigned long long key[kPatchVpt];
+    float nx[kPatchVpt], ny[kPatchVpt], nz[kPatchVpt];
+    bool live[kPatchVpt];
+    {
+      float px[kPatchVpt], py[kPatchVpt], pz[kPatchVpt];
+      bool ok[kPatchVpt];
+#pragma unroll
+      for (int j = 0; j < kPatchVpt; ++j) {
+        const int v = b0 + j * kPatchBlock + tid;
+        ok[j] = v < m.n;
+        float x = 0.f, y = 0.f, z = 0.f;
+        if (ok[j]) {
+          x = m.x[v];
+          y = m.y[v];
+          z = m.z[v];
+        }
+        transform(R, x, y, z, px[j], py[j], pz[j]);
+      }
+      Cell cl[kPatchVpt];
+      float c[kPatchVpt][8];
+#pragma unroll
+      for (int j = 0; j < kPatchVpt; ++j) cl[j] = locate(g, px[j], py[j], pz[j]);
+#pragma unroll
+      for (int j = 0; j < kPatchVpt; ++j) gather<DT, LAYOUT>(g, cl[j], c[j]);
+#pragma unroll
+      for (int j = 0; j < kPatchVpt; ++j) {
+        float phi, gx, gy, gz;
+        trilinear(c[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
+        live[j] = ok[j] & cl[j].inside & (phi < A.margin);
+        nx[j] = ny[j] = nz[j] = 0.f;
+        key[j] = 0ull;
+        if (live[j]) {
+          normalize(gx, gy, gz, nx[j], ny[j], nz[j]);
+          key[j] = make_key(-phi, (unsigned)(b0 + j * kPatchBlock + tid));
+        }
+      }
+    }
+    // Assign, against the patches present as the batch begins
+    const int np0 = s_np;
+#pragma unroll
+    for (int j = 0; j < kPatchVpt; ++j) {
+      if (!live[j]) continue;
+      int best = -1;
+      float bd = 0.f;
+      for (int p = 0; p < np0; ++p) {
+        const float d = dot3_nofma(nx[j], ny[j], nz[j], s_pn[p][0], s_pn[p][1], s_pn[p][2]);
+        if (d >= cs && (best < 0 || d > bd)) {
+          best = p;
+          bd = d;
+        }
+      }
+      if (best >= 0) {
+        atomicAdd(&s_pmem[best], 1);
+        atomicMax(&s_pkey[best], key[j]);
+        live[j] = false;
+      }
+    }
+    __syncthreads();
+    // FindDeepest / BinReduce / AddPatch while candidates remain
+    for (;;) {
+      unsigned long long mk = 0ull;
+#pragma unroll
+      for (int j = 0; j < kPatchVpt; ++j)
+        if (live[j] && key[j] > mk) mk = key[j];
+      mk = wave_max_u64(mk);
+      if (lane == 0) s_wkey[wave] = mk;
+      __syncthreads();
+      unsigned long long best = s_wkey[0];
+#pragma unroll
+      for (int w = 1; w < kPatchBlock / 64; ++w) best = s_wkey[w] > best ? s_wkey[w] : best;
+      if (best == 0ull) break;  // the same value in every thread
+#pragma unroll
+      for (int j = 0; j < kPatchVpt; ++j)
+        if (live[j] && key[j] == best) {  // keys are unique: one owner
+          s_bn[0] = nx[j];
+          s_bn[1] = ny[j];
+          s_bn[2] = nz[j];
+        }
+      __syncthreads();  // s_bn written; every thread has read s_wkey
+      const float bx = s_bn[0], by = s_bn[1], bz = s_bn[2];
+      int cnt = 0;
+#pragma unroll
+      for (int j = 0; j < kPatchVpt; ++j)
+        if (live[j] && (key[j] == best || dot3_nofma(bx, by, bz, nx[j], ny[j], nz[j]) >= cs)) {
+          ++cnt;
+          live[j] = false;
+        }
+      cnt = wave_sum_i32(cnt);
+      // the most similar existing patch (needed only when the list is full)
+      const int np = s_np;
+      float d = -__builtin_inff();
+      int pj = 0x7fffffff;
+      if (np >= P.n_max && tid < np) {
+        d = dot3_nofma(bx, by, bz, s_pn[tid][0], s_pn[tid][1], s_pn[tid][2]);
+        pj = tid;
+      }
+      wave_argmax(d, pj);
+      if (lane == 0) {
+        s_wint[wave] = cnt;
+        s_wd[wave] = d;
+        s_wkey[wave] = (unsigned long long)(unsigned)pj;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int members = 0;
+        float dd = -__builtin_inff();
+        int jj = 0x7fffffff;
+        for (int w = 0; w < kPatchBlock / 64; ++w) {
+          members += s_wint[w];
+          const int pw = (int)s_wkey[w];
+          if (s_wd[w] > dd || (s_wd[w] == dd && pw < jj)) {
+            dd = s_wd[w];
+            jj = pw;
+          }
+        }
+        int slot = -1;
+        if (np < P.n_max) {
+          slot = np;
+          s_np = np + 1;
+        } else if ((float)members * key_depth(best) > (float)s_pmem[jj] * key_depth(s_pkey[jj])) {
+          slot = jj;
+        }
+        if (slot >= 0) {
+          s_pn[slot][0] = bx;
+          s_pn[slot][1] = by;
+          s_pn[slot][2] = bz;
+          s_pkey[slot] = best;
+          s_pmem[slot] = members;
+          s_pfound[slot] = (int)key_vidx(best);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // the patch list, each with its deepest member's record
+  const int np = s_np;
+  if (tid == 0) P.count[e] = np;
+  const long long S = (long long)A.n_env * P.n_max;
+  for (int p = tid; p < P.n_max; p += kPatchBlock) {
+    const long long s = (long long)e * P.n_max + p;
+    if (p < np) {
+      const unsigned v = key_vidx(s_pkey[p]);
+      float xb, yb, zb;
+      transform(R, m.x[v], m.y[v], m.z[v], xb, yb, zb);
+      P.founder[s] = s_pfound[p];
+      P.vidx[s] = (int)v;
+      P.depth[s] = key_depth(s_pkey[p]);
+      P.members[s] = s_pmem[p];
+      P.normal[s] = s_pn[p][0];
+      P.normal[S + s] = s_pn[p][1];
+      P.normal[2 * S + s] = s_pn[p][2];
+      P.point[s] = xb;
+      P.point[S + s] = yb;
+      P.point[2 * S + s] = zb;
+    } else {
+      P.founder[s] = -1;
+      P.vidx[s] = -1;
+      P.depth[s] = 0.f;
+      P.members[s] = 0;
+      P.normal[s] = P.normal[S + s] = P.normal[2 * S + s] = 0.f;
+      P.point[s] = P.point[S + s] = P.point[2 * S + s] = 0.f;
+    }
+  }
+}
+
+}  // namespace
+
+template <int DT, int LAYOUT>
+hipError_t patches_launch(const FwdArgs& a, const PatchArgs& p, hipStream_t s) {
+  hipError_t e = mark(false, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_patches<DT, LAYOUT>), dim3(a.n_env), dim3(kPatchBlock), 0, s, a, p);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return mark(true, s);
+}
+
+template <int DT>
+hipError_t patches_layout(const FwdArgs& a, const PatchArgs& p, int layout, hipStream_t s) {
+  if (layout == FC_LAYOUT_BRICK) return patches_launch<DT, FC_LAYOUT_BRICK>(a, p, s);
+  if (layout == FC_LAYOUT_SLAB) return patches_launch<DT, FC_LAYOUT_SLAB>(a, p, s);
+  if (layout == FC_LAYOUT_SPARSE) return patches_launch<DT, FC_LAYOUT_SPARSE>(a, p, s);
+  return patches_launch<DT, FC_LAYOUT_LINEAR>(a, p, s);
+}
+
+hipError_t launch_patches(const FwdArgs& a, const PatchArgs& p, int dtype, int layout, hipStream_t s,
+                          const KernelMarks* m) {
+  if (a.n_env <= 0) return hipSuccess;
+  const MarksScope scope(m);
+  switch (dtype) {
+    case kF32: return patches_layout<kF32>(a, p, layout, s);
+    case kF16: return patches_layout<kF16>(a, p, layout, s);
+    case kBF16: return patches_layout<kBF16>(a, p, layout, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fcimpl

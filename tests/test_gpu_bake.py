@@ -157,3 +157,45 @@ def test_full_size_lipschitz_and_sign(full_bake):
     outside = (rho > spec.Rmaj + 2 * h) | (zz < -2 * h) | (zz > spec.L + 2 * h)
     assert bool((out[inside] < 0).all()) and bool((out[outside] > 0).all())
     assert int(inside.sum()) > 100000 and int(outside.sum()) > 1000000
+
+
+def test_baked_grid_is_queried_like_a_sampled_one():
+    """Section III-A's asset path: the mesh is baked at initialisation and the
+    result is body B of the contact queries.  The GPU bake of a small threaded
+    rod feeds a batch (the baked tensor as a linear FP32 grid); its queries
+    match the FP64 oracle query on the oracle's own bake of the same mesh
+    within the bake tolerance plus the query tolerance."""
+    torch = torch_gpu()
+    from _gpu_common import DEPTH_TOL_F32, to_np as dict_to_np
+    from oracle import query as OQ
+
+    v, t = W.bolt_mesh(0.7e-3, 2e-3, 3e-3, 24, 12)
+    dims, origin, h = (30, 30, 25), tuple(float(np.float32(x)) for x in (-2.9e-3, -2.9e-3, -0.9e-3)), float(np.float32(0.2e-3))
+    baked = fc.fc_bake_sdf(fc.BakeTable(v, t), dims, origin, h)
+    torch.cuda.synchronize()
+    g_gpu = W.Grid(values=to_np(baked).astype(np.float32), dtype="f32", origin=origin, h=h)
+    rng = np.random.default_rng(5)
+    probe = W.Mesh(verts=rng.uniform(-2.5e-3, 2.5e-3, (3000, 3)).astype(np.float32) + np.float32([0, 0, 1.5e-3]))
+    n_env = 8
+    q = np.tile([0.0, 0.0, 0.0, 1.0], (n_env, 1)).T
+    tr = rng.uniform(-0.3e-3, 0.3e-3, (3, n_env))
+    w = W.Workload(name="baked-rod", grids=[g_gpu], meshes=[probe], env_grid=np.zeros(n_env, np.int32),
+                   env_mesh=np.zeros(n_env, np.int32), pose=W.pack_pose(q, tr), bins=W.fibonacci_bins(16),
+                   margin=0.0, meta={})
+    b = fc.Batch.from_workload(w)
+    c = b.new_candidates()
+    fc.fc_sdf_query(b, fc.pose_tensor(w.pose), cand=c)
+    torch.cuda.synchronize()
+    c = dict_to_np(c)
+    ref_vals = OB.bake(v.astype(np.float64), t, dims, origin, h)  # [nz][ny][nx]
+    tol = tol_of(v.astype(np.float32), dims, origin, h) + DEPTH_TOL_F32
+    off = w.env_query_offsets()
+    n_in = 0
+    for e in range(n_env):
+        xb = OQ.transform(w.pose[:, e], probe.verts)
+        phi, _, ins, _ = OQ.sample(ref_vals, origin, h, dims, xb)
+        got = c["phi"][off[e]:off[e + 1]].astype(np.float64)
+        ok = ins & np.isfinite(got)
+        assert np.max(np.abs(got[ok] - phi[ok])) <= tol
+        n_in += int(ok.sum())
+    assert n_in > 10000
