@@ -50,21 +50,21 @@ __device__ __forceinline__ void wave_argmax(float& d, int& p) {
 }
 
 // One workgroup per environment.  For each batch of 1024 vertices: Generate
-// the candidates (the vertex query's values, bit for bit), Assign each to the
-// most similar patch that existed when the batch began, then repeat
-// FindDeepest / BinReduce / AddPatch until no candidate remains.  Patches live
-// in LDS; member counts and deepest keys are order-independent atomics.
+// the candidates (the vertex query's values, bit for bit) and compact them in
+// LDS; Assign each to the most similar patch that existed when the batch
+// began (all waves; member counts and deepest keys are order-independent LDS
+// atomics); then one wave repeats FindDeepest / BinReduce / AddPatch until no
+// candidate remains.  Patches live in LDS.
 template <int DT, int LAYOUT>
 __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P) {
   __shared__ float s_pn[kPatchMax][3];
   __shared__ unsigned long long s_pkey[kPatchMax];
   __shared__ int s_pmem[kPatchMax];
   __shared__ int s_pfound[kPatchMax];
-  __shared__ unsigned long long s_wkey[kPatchBlock / 64];
-  __shared__ int s_wint[kPatchBlock / 64];
-  __shared__ float s_wd[kPatchBlock / 64];
-  __shared__ float s_bn[3];
   __shared__ int s_np;
+  __shared__ unsigned long long s_ck[kPatchBatch];  // the batch's candidates, compacted
+  __shared__ float s_cn[kPatchBatch][3];
+  __shared__ int s_nc;
 
   const int e = blockIdx.x;
   const int gm = A.envs[e].gm;
@@ -77,7 +77,11 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
   __syncthreads();
 
   for (int b0 = 0; b0 < m.n; b0 += kPatchBatch) {
-    // Generate
+    if (tid == 0) s_nc = 0;
+    __syncthreads();
+    // Generate, then compact the candidates into LDS: every later step is
+    // independent of their order, and each thread then holds ceil(nc / 256)
+    // of them instead of 4 vertices mostly without a candidate
     unsigned long long key[kPatchVpt];
     float nx[kPatchVpt], ny[kPatchVpt], nz[kPatchVpt];
     bool live[kPatchVpt];
@@ -106,12 +110,31 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
       for (int j = 0; j < kPatchVpt; ++j) {
         float phi, gx, gy, gz;
         trilinear(c[j], cl[j].tx, cl[j].ty, cl[j].tz, phi, gx, gy, gz);
-        live[j] = ok[j] & cl[j].inside & (phi < A.margin);
-        nx[j] = ny[j] = nz[j] = 0.f;
+        if (ok[j] & cl[j].inside & (phi < A.margin)) {
+          float ux, uy, uz;
+          normalize(gx, gy, gz, ux, uy, uz);
+          const int pos = atomicAdd(&s_nc, 1);
+          s_ck[pos] = make_key(-phi, (unsigned)(b0 + j * kPatchBlock + tid));
+          s_cn[pos][0] = ux;
+          s_cn[pos][1] = uy;
+          s_cn[pos][2] = uz;
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const int nc = s_nc;
+#pragma unroll
+      for (int j = 0; j < kPatchVpt; ++j) {
+        const int i = j * kPatchBlock + tid;
+        live[j] = i < nc;
         key[j] = 0ull;
+        nx[j] = ny[j] = nz[j] = 0.f;
         if (live[j]) {
-          normalize(gx, gy, gz, nx[j], ny[j], nz[j]);
-          key[j] = make_key(-phi, (unsigned)(b0 + j * kPatchBlock + tid));
+          key[j] = s_ck[i];
+          nx[j] = s_cn[i][0];
+          ny[j] = s_cn[i][1];
+          nz[j] = s_cn[i][2];
         }
       }
     }
@@ -132,75 +155,65 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
       if (best >= 0) {
         atomicAdd(&s_pmem[best], 1);
         atomicMax(&s_pkey[best], key[j]);
-        live[j] = false;
+        s_ck[j * kPatchBlock + tid] = 0ull;  // assigned: out of the loop below
       }
     }
     __syncthreads();
-    // FindDeepest / BinReduce / AddPatch while candidates remain
-    for (;;) {
-      unsigned long long mk = 0ull;
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j)
-        if (live[j] && key[j] > mk) mk = key[j];
-      mk = wave_max_u64(mk);
-      if (lane == 0) s_wkey[wave] = mk;
-      __syncthreads();
-      unsigned long long best = s_wkey[0];
-#pragma unroll
-      for (int w = 1; w < kPatchBlock / 64; ++w) best = s_wkey[w] > best ? s_wkey[w] : best;
-      if (best == 0ull) break;  // the same value in every thread
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j)
-        if (live[j] && key[j] == best) {  // keys are unique: one owner
-          s_bn[0] = nx[j];
-          s_bn[1] = ny[j];
-          s_bn[2] = nz[j];
-        }
-      __syncthreads();  // s_bn written; every thread has read s_wkey
-      const float bx = s_bn[0], by = s_bn[1], bz = s_bn[2];
-      int cnt = 0;
-#pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j)
-        if (live[j] && (key[j] == best || dot3_nofma(bx, by, bz, nx[j], ny[j], nz[j]) >= cs)) {
-          ++cnt;
-          live[j] = false;
-        }
-      cnt = wave_sum_i32(cnt);
-      // the most similar existing patch (needed only when the list is full)
-      const int np = s_np;
-      float d = -__builtin_inff();
-      int pj = 0x7fffffff;
-      if (np >= P.n_max && tid < np) {
-        d = dot3_nofma(bx, by, bz, s_pn[tid][0], s_pn[tid][1], s_pn[tid][2]);
-        pj = tid;
-      }
-      wave_argmax(d, pj);
-      if (lane == 0) {
-        s_wint[wave] = cnt;
-        s_wd[wave] = d;
-        s_wkey[wave] = (unsigned long long)(unsigned)pj;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        int members = 0;
-        float dd = -__builtin_inff();
-        int jj = 0x7fffffff;
-        for (int w = 0; w < kPatchBlock / 64; ++w) {
-          members += s_wint[w];
-          const int pw = (int)s_wkey[w];
-          if (s_wd[w] > dd || (s_wd[w] == dd && pw < jj)) {
-            dd = s_wd[w];
-            jj = pw;
+    // FindDeepest / BinReduce / AddPatch while candidates remain: one wave,
+    // no workgroup barrier per patch.  Each lane owns the compacted entries
+    // i = lane (mod 64) and is the only one to clear them; lane 0 writes the
+    // patch list, which the wave reads back after a wave barrier.
+    if (wave == 0) {
+      const int nc = s_nc;
+      int np = s_np;
+      for (;;) {
+        unsigned long long mk = 0ull;
+        int mi = -1;
+        for (int i = lane; i < nc; i += 64) {
+          const unsigned long long k = s_ck[i];
+          if (k > mk) {
+            mk = k;
+            mi = i;
           }
         }
+        const unsigned long long best = wave_max_u64(mk);
+        if (best == 0ull) break;  // the same value in every lane
+        // the owner's normal, broadcast (keys are unique: one owner lane)
+        const unsigned long long own = __ballot(mk == best);
+        const int ol = __ffsll((long long)own) - 1;
+        float ox = 0.f, oy = 0.f, oz = 0.f;
+        if (mk == best) {
+          ox = s_cn[mi][0];
+          oy = s_cn[mi][1];
+          oz = s_cn[mi][2];
+        }
+        const float bx = __shfl(ox, ol), by = __shfl(oy, ol), bz = __shfl(oz, ol);
+        int cnt = 0;
+        for (int i = lane; i < nc; i += 64) {
+          const unsigned long long k = s_ck[i];
+          if (k != 0ull && (k == best || dot3_nofma(bx, by, bz, s_cn[i][0], s_cn[i][1], s_cn[i][2]) >= cs)) {
+            ++cnt;
+            s_ck[i] = 0ull;
+          }
+        }
+        const int members = wave_sum_i32(cnt);
         int slot = -1;
         if (np < P.n_max) {
-          slot = np;
-          s_np = np + 1;
-        } else if ((float)members * key_depth(best) > (float)s_pmem[jj] * key_depth(s_pkey[jj])) {
-          slot = jj;
+          slot = np++;
+        } else {  // the most similar existing patch, lowest index on ties
+          float d = -__builtin_inff();
+          int pj = 0x7fffffff;
+          for (int q = lane; q < np; q += 64) {
+            const float dq = dot3_nofma(bx, by, bz, s_pn[q][0], s_pn[q][1], s_pn[q][2]);
+            if (dq > d) {  // ascending q: the first maximum stays
+              d = dq;
+              pj = q;
+            }
+          }
+          wave_argmax(d, pj);
+          if ((float)members * key_depth(best) > (float)s_pmem[pj] * key_depth(s_pkey[pj])) slot = pj;
         }
-        if (slot >= 0) {
+        if (slot >= 0 && lane == 0) {
           s_pn[slot][0] = bx;
           s_pn[slot][1] = by;
           s_pn[slot][2] = bz;
@@ -208,9 +221,13 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
           s_pmem[slot] = members;
           s_pfound[slot] = (int)key_vidx(best);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      __syncthreads();
+      if (lane == 0) s_np = np;
     }
+    __syncthreads();
   }
   // the patch list, each with its deepest member's record
   const int np = s_np;
