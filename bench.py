@@ -341,8 +341,8 @@ def measure_forms(w32, device, n, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n-env", type=int, default=1000)
     ap.add_argument("--layout", default=None, choices=[None, "linear", "brick", "slab"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
