@@ -156,6 +156,80 @@ def cpu_baseline(w, n_sample):
                        f"penalty adjoint, one thread, {dt:.1f} s")
 
 
+_PAR = {}
+
+
+def _par_init(grid_path, verts, pose, bins, margin, origin, h):
+    """Worker set-up for the parallel oracle run: the grid memory-mapped."""
+    from paper_2205_03532_amd import workloads as W
+
+    g = W.Grid(values=np.load(grid_path, mmap_mode="r"), dtype="f32", origin=origin, h=h)
+    _PAR.update(grid=g, verts=verts, pose=pose, bins=bins, margin=margin)
+
+
+def _par_envs(envs):
+    """Oracle query + per-env penalty adjoint for a list of envs (one thread);
+    returns the query count and the candidates' (env, vidx, depth, bin)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import adjoint as OA
+    from oracle import query as OQ
+
+    g = _PAR["grid"]
+    with threadpool_limits(limits=1):
+        vals = OQ.grid_values_f64(np.asarray(g.values), g.dtype)
+        out = []
+        for e in envs:
+            r = OQ.query_env(g, _PAR["verts"], _PAR["pose"][:, e], _PAR["margin"], _PAR["bins"], vals)
+            OA.penalty_env(g, _PAR["verts"], _PAR["pose"][:, e], K_PENALTY, vals)
+            c = np.nonzero(r["cand"])[0]
+            out.append((e, c, r["depth"][c].astype(np.float32), r["bin"][c]))
+    return len(envs) * len(_PAR["verts"]), out
+
+
+def cpu_baseline_parallel(w, procs):
+    """The same oracle over all envs in a pool of worker processes (spawned,
+    grid memory-mapped from a temporary file), the exact reduction in the
+    parent.  Wall time includes the pool's start-up."""
+    import multiprocessing as mp
+    import tempfile
+
+    from oracle import reduce as ORD
+
+    g = w.grids[0]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "grid.npy")
+        np.save(path, np.ascontiguousarray(g.values))
+        chunks = [list(range(i, w.n_env, procs)) for i in range(procs)]
+        t0 = time.perf_counter()
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(procs, initializer=_par_init,
+                      initargs=(path, w.meshes[0].verts, w.pose, w.bins, w.margin, g.origin, g.h)) as pool:
+            parts = pool.map_async(_par_envs, chunks).get(timeout=300)  # a worker that dies cannot hang the bench
+        env = np.concatenate([np.full(len(c), e) for _, lst in parts for e, c, _, _ in lst])
+        vidx = np.concatenate([c for _, lst in parts for _, c, _, _ in lst])
+        depth = np.concatenate([dd for _, lst in parts for _, _, dd, _ in lst])
+        bins = np.concatenate([b for _, lst in parts for _, _, _, b in lst])
+        ORD.reduce_contacts(env, vidx, depth, bins, np.ones(len(env), bool), w.n_env, w.K)
+        dt = time.perf_counter() - t0
+    q = sum(n for n, _ in parts)
+    return dict(value=q / dt, unit="queries/s", cores=procs, kind="oracle",
+                sample=f"all {w.n_env} envs ({q} queries): FP64 query + penalty adjoint in {procs} spawned "
+                       f"processes, exact reduction in the parent, {dt:.1f} s including the pool's start-up")
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpus_visible": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0))}
+
+
 def depth_check(w, cand_phi, n_env=4):
     from oracle import query as OQ
 
@@ -433,6 +507,9 @@ def main():
     k_one, kid = batch.read_timing()
     assert len(k_one) == n and np.all(kid == fc.FC_KERNEL_QUERY_BACKWARD)
 
+    def quantiles(a):
+        return {f"p{q}": float(np.percentile(a, q)) for q in (10, 50, 90)}
+
     # the achievable gather rate of this path: the same kernel loop and loads with no
     # arithmetic (fc_gather_probe), timed the same way
     sink = torch.zeros(1, device=dev)
@@ -467,6 +544,12 @@ def main():
     k_fwd, k_bwd = k_sep[kid == fc.FC_KERNEL_FORWARD], k_sep[kid == fc.FC_KERNEL_BACKWARD]
     same = all(torch.equal(out[k], out2[k]) for k in out) and all(
         torch.equal(grads[k], grads2[k]) for k in ("loss", "d_pose", "d_verts"))
+
+    # the unfused forward: candidates written, then the reduction reads them
+    cand_u = batch.new_candidates()
+    unf_ms = time_calls(lambda: (fc.fc_sdf_query(batch, pose, cand=cand_u),
+                                 fc.fc_contact_reduce(batch, pose, cand_u, out2)), n, args.warmup)
+    del cand_u
 
     bpq = alg_bytes_per_query(args.dtype)
     o_avg, f_avg, b_avg = float(one_ms.mean()), float(fwd_ms.mean()), float(bwd_ms.mean())
@@ -511,6 +594,10 @@ def main():
         "separate_fwd_then_bwd_queries_per_s": Q / ((f_avg + b_avg) * 1e-3),
         "separate_equals_one_pass": bool(same),
         "call_ms": {"query_and_backward": o_avg, "query": f_avg, "backward": b_avg},
+        "call_ms_quantiles": {"query_and_backward": quantiles(one_ms), "query": quantiles(fwd_ms),
+                              "backward": quantiles(bwd_ms)},
+        "kernel_ms_quantiles": {"k_query_backward": quantiles(k_one)},
+        "fwd_unfused_queries_per_s": Q / (unf_ms * 1e-3),
         "kernel_ms": {"k_query_backward": kms, "k_forward": float(k_fwd.mean()), "k_backward": float(k_bwd.mean())},
         "max_depth_err_m": derr,
         "roofline": {
@@ -539,8 +626,14 @@ def main():
                         "nutbolt_patch_reduction": measure_patches(batch, pose, n, args.warmup)}
         res["forms"].update(measure_forms(w, dev, n, args.warmup))
         res["forms"]["m4_bolt_mesh_bake"] = measure_bake(n, args.warmup, 0 if args.no_cpu_baseline else 100)
+    res["host"] = host_info()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, w.n_env))
+        if args.dtype == "f32":
+            try:
+                res["cpu_baseline_parallel"] = cpu_baseline_parallel(w, min(16, len(os.sched_getaffinity(0))))
+            except Exception as exc:  # reported, never fatal: the GPU figures above stand
+                res["cpu_baseline_parallel"] = {"skipped": f"{type(exc).__name__}: {exc}"}
     print(json.dumps(res), flush=True)
 
 
