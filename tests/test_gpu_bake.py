@@ -199,3 +199,17 @@ def test_baked_grid_is_queried_like_a_sampled_one():
         assert np.max(np.abs(got[ok] - phi[ok])) <= tol
         n_in += int(ok.sum())
     assert n_in > 10000
+
+
+def test_mesh_far_from_the_origin():
+    """A cube 100 m along x from a grid near the origin: distances of about
+    100 m, so the cull slack must follow the mesh's coordinates; the values
+    stay within the tolerance scaled by the largest coordinate."""
+    torch_gpu()
+    v, t = W.cube_mesh(0.5)
+    v = np.asarray(v, dtype=np.float32) + np.float32([100.0, 0.0, 0.0])
+    dims, origin, h = (11, 9, 7), (-0.5, -0.4, -0.3), 0.1
+    got = bake_gpu(v, t, dims, origin, h)
+    ref = OB.bake(v.astype(np.float64), t, dims, origin, h)
+    compare(got, ref, tol_of(v, dims, origin, h))
+    assert np.all(got >= 99.0 - 1e-4)  # the nearest face is at x = 99.5, the grid reaches x = 0.5

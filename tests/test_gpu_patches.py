@@ -142,3 +142,18 @@ def test_patch_kernel_timing_id():
     ms, kid = b.read_timing()
     b.set_timing(0)
     assert list(kid) == [fc.FC_KERNEL_FORWARD, fc.FC_KERNEL_PATCHES] and ms[1] > 0
+
+
+def test_positive_margin_gives_negative_depths():
+    """margin = 1 mm: candidates include points outside B (depth < 0), whose
+    keys and AddPatch values are negative; the decisions still match the
+    oracle bit for bit."""
+    import dataclasses
+
+    torch_gpu()
+    w = dataclasses.replace(W.subset(W.torus_workload(), range(24)), margin=1e-3)
+    b = fc.Batch.from_workload(w)
+    c, out = run(b, fc.pose_tensor(w.pose), 12, float(np.float32(np.cos(np.radians(20.0)))))
+    st = check_patches(w, c, out, 12, float(np.float32(np.cos(np.radians(20.0)))), range(w.n_env))
+    assert (c["phi"][c["bin"] >= 0] > 0).sum() > 1000  # non-penetrating candidates took part
+    assert st["dropped"] > 0
