@@ -188,3 +188,41 @@ def test_faces_on_sparse_equal_brick():
         outs.append((to_np(c), to_np(o)))
     assert_same(outs[0][0], outs[1][0])
     assert_same(outs[0][1], outs[1][1])
+
+
+def test_sparse_graph_replay_and_autograd():
+    """The sparse layout under hipGraph replay (with eager work between
+    replays) and behind the autograd function: the same bits as eager calls
+    on the same batch, and the autograd gradients equal the brick layout's."""
+    torch = torch_gpu()
+    from paper_2205_03532_amd.autograd import penalty
+
+    w = W.subset(W.nut_bolt_workload(), range(0, 1000, 25))
+    band = float(np.float32(4 * w.grids[0].h))
+    b = fc.Batch.from_workload(w, layout="sparse", band=band)
+    pose = fc.pose_tensor(w.pose)
+    ref_o, ref_g = run_one_pass(b, pose)
+    out, gr = b.new_contacts(), b.new_grads(per_env=False)
+    graph = fc.fc_graph_create(b, pose, fused_out=out, k=1e4, grads=gr)
+    for _ in range(3):
+        for t in list(out.values()) + [v for k, v in gr.items() if k != "per_env"]:
+            t.fill_(7)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        assert_same(to_np(out), ref_o)
+        assert_same(to_np({k: v for k, v in gr.items() if k != "per_env"}),
+                    {k: v for k, v in ref_g.items() if k != "per_env"})
+    del graph
+    grads = []
+    for bb in (b, fc.Batch.from_workload(w, layout="brick")):
+        for mt in bb.mesh_tensors:
+            mt.requires_grad_(True)
+        loss, xi = penalty(bb, pose, 1e4)
+        loss.sum().backward()
+        grads.append((loss.detach().cpu().numpy(), xi.grad.cpu().numpy(), bb.mesh_tensors[0].grad.cpu().numpy()))
+        for mt in bb.mesh_tensors:
+            mt.requires_grad_(False)
+            mt.grad = None
+    for a_, b_ in zip(grads[0], grads[1]):
+        assert np.array_equal(a_.view(np.uint32), b_.view(np.uint32))
