@@ -138,21 +138,24 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
         }
       }
     }
-    // Assign, against the patches present as the batch begins
+    // Assign, against the patches present as the batch begins.  The first
+    // patch of largest dot over all patches is the patch of largest dot
+    // among the similar ones (lowest index on ties) whenever it is similar
+    // itself, and no patch is similar otherwise.
     const int np0 = s_np;
 #pragma unroll
     for (int j = 0; j < kPatchVpt; ++j) {
       if (!live[j]) continue;
       int best = -1;
-      float bd = 0.f;
+      float bd = -INFINITY;
       for (int p = 0; p < np0; ++p) {
         const float d = dot3_nofma(nx[j], ny[j], nz[j], s_pn[p][0], s_pn[p][1], s_pn[p][2]);
-        if (d >= cs && (best < 0 || d > bd)) {
+        if (d > bd) {
           best = p;
           bd = d;
         }
       }
-      if (best >= 0) {
+      if ((best >= 0) & (bd >= cs)) {
         atomicAdd(&s_pmem[best], 1);
         atomicMax(&s_pkey[best], key[j]);
         s_ck[j * kPatchBlock + tid] = 0ull;  // assigned: out of the loop below
