@@ -166,19 +166,21 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
     // no workgroup barrier per patch.  Each lane owns the compacted entries
     // i = lane (mod 64) and is the only one to clear them; lane 0 writes the
     // patch list, which the wave reads back after a wave barrier.
+    // The BinReduce pass visits every entry that is left after it, so it
+    // also finds the next FindDeepest's lane maxima: one pass per patch.
     if (wave == 0) {
       const int nc = s_nc;
       int np = s_np;
-      for (;;) {
-        unsigned long long mk = 0ull;
-        int mi = -1;
-        for (int i = lane; i < nc; i += 64) {
-          const unsigned long long k = s_ck[i];
-          if (k > mk) {
-            mk = k;
-            mi = i;
-          }
+      unsigned long long mk = 0ull;
+      int mi = -1;
+      for (int i = lane; i < nc; i += 64) {
+        const unsigned long long k = s_ck[i];
+        if (k > mk) {
+          mk = k;
+          mi = i;
         }
+      }
+      for (;;) {
         const unsigned long long best = wave_max_u64(mk);
         if (best == 0ull) break;  // the same value in every lane
         // the owner's normal, broadcast (keys are unique: one owner lane)
@@ -192,11 +194,17 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
         }
         const float bx = __shfl(ox, ol), by = __shfl(oy, ol), bz = __shfl(oz, ol);
         int cnt = 0;
+        mk = 0ull;
+        mi = -1;
         for (int i = lane; i < nc; i += 64) {
           const unsigned long long k = s_ck[i];
-          if (k != 0ull && (k == best || dot3_nofma(bx, by, bz, s_cn[i][0], s_cn[i][1], s_cn[i][2]) >= cs)) {
+          if (k == 0ull) continue;
+          if (k == best || dot3_nofma(bx, by, bz, s_cn[i][0], s_cn[i][1], s_cn[i][2]) >= cs) {
             ++cnt;
             s_ck[i] = 0ull;
+          } else if (k > mk) {  // remains: a candidate for the next FindDeepest
+            mk = k;
+            mi = i;
           }
         }
         const int members = wave_sum_i32(cnt);
