@@ -21,19 +21,49 @@ __device__ __forceinline__ float dot3_nofma(float ax, float ay, float az, float 
   return (ax * bx + ay * by) + az * bz;
 }
 
+// Wave-wide reductions on the data-parallel primitives instead of LDS
+// permutes: DPP quad xor 1 and xor 2, the 8-lane and 16-lane mirrors (with
+// every lane of a group holding the group's result, a mirror pairs the two
+// halves), a ds_swizzle xor 16, then lanes 0 and 32 read as scalars.  The
+// result is the same in every lane.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+  return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ unsigned swz16_u32(unsigned v) {
+  return (unsigned)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);  // bit mode: lane i <- lane i ^ 16
+}
+__device__ __forceinline__ unsigned long long join64(unsigned lo, unsigned hi) {
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long max64_with(unsigned long long v, unsigned lo, unsigned hi) {
+  const unsigned long long w = join64(lo, hi);
+  return w > v ? w : v;
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long max64_dpp(unsigned long long v) {
+  return max64_with(v, dpp_u32<CTRL>((unsigned)v), dpp_u32<CTRL>((unsigned)(v >> 32)));
+}
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long w = __shfl_xor(v, o);
-    v = w > v ? w : v;
-  }
-  return v;
+  v = max64_dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = max64_dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = max64_dpp<0x141>(v);  // lane i <- lane 7-i within each 8 lanes
+  v = max64_dpp<0x140>(v);  // lane i <- lane 15-i within each row
+  v = max64_with(v, swz16_u32((unsigned)v), swz16_u32((unsigned)(v >> 32)));
+  const unsigned long long a = join64((unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 0),
+                                      (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 0));
+  const unsigned long long b = join64((unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 32),
+                                      (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 32));
+  return a > b ? a : b;
 }
 
 __device__ __forceinline__ int wave_sum_i32(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += (int)dpp_u32<0xB1>((unsigned)v);
+  v += (int)dpp_u32<0x4E>((unsigned)v);
+  v += (int)dpp_u32<0x141>((unsigned)v);
+  v += (int)dpp_u32<0x140>((unsigned)v);
+  v += (int)swz16_u32((unsigned)v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32);
 }
 
 // (d, p) with the largest d, the lowest p on ties
@@ -192,7 +222,9 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
           oy = s_cn[mi][1];
           oz = s_cn[mi][2];
         }
-        const float bx = __shfl(ox, ol), by = __shfl(oy, ol), bz = __shfl(oz, ol);
+        const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ox), ol));
+        const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(oy), ol));
+        const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(oz), ol));
         int cnt = 0;
         mk = 0ull;
         mi = -1;
