@@ -18,6 +18,14 @@ evaluated at xi = 0.  ``fd_*`` difference the same loss in FP64: translations
 move x_B by +-h e_i; rotations turn x_B about B's origin by +-h about e_i.
 Where a perturbed vertex leaves its trilinear cell the loss has a kink; such
 components are flagged and an error bound for them is returned.
+
+Every function samples the dense grid unless given ``sampler``, a callable
+x -> (phi, grad, inside, cell) over B-frame points, such as the narrow-band
+sparse grid's field (``oracle.sparse.sparse_sampler``).  That field is the
+dense interpolant in stored bricks and a coarse trilinear interpolant in the
+others; its kinks lie on fine cell faces (coarse cell faces are fine cell
+faces too), so the fine cell still flags every kink, and a few smooth
+crossings besides, which only widens the bound.
 """
 from __future__ import annotations
 
@@ -26,22 +34,28 @@ import numpy as np
 from . import query as Q
 
 
-def _terms(vals64, grid, x, k):
-    phi, grad, inside, cell = Q.sample(vals64, grid.origin, grid.h, grid.dims, x)
+def dense_sampler(grid, vals64=None):
+    """x -> (phi, grad, inside, cell) of the grid's trilinear interpolant."""
+    if vals64 is None:
+        vals64 = Q.grid_values_f64(grid.values, grid.dtype)
+    return lambda x: Q.sample(vals64, grid.origin, grid.h, grid.dims, x)
+
+
+def _terms(sampler, x, k):
+    phi, grad, inside, cell = sampler(x)
     with np.errstate(invalid="ignore"):
         act = inside & (phi < 0.0)
     term = np.where(act, 0.5 * k * np.where(act, phi, 0.0) ** 2, 0.0)
     return term, phi, grad, act, cell
 
 
-def penalty_env(grid, verts, pose, k, vals64=None):
+def penalty_env(grid, verts, pose, k, vals64=None, sampler=None):
     """(loss, d_twist (6,), d_verts (n,3)) for one environment, FP64."""
-    if vals64 is None:
-        vals64 = Q.grid_values_f64(grid.values, grid.dtype)
+    sampler = sampler or dense_sampler(grid, vals64)
     pose = np.asarray(pose, dtype=np.float64)
     R = Q.rotation_from_quaternion(pose[:4])
     xb = Q.transform(pose, verts)
-    term, phi, grad, act, _ = _terms(vals64, grid, xb, k)
+    term, phi, grad, act, _ = _terms(sampler, xb, k)
     w = np.where(act[:, None], k * np.where(act, phi, 0.0)[:, None] * grad, 0.0)
     d_rho = w.sum(axis=0)
     d_omega = np.cross(xb, w).sum(axis=0)
@@ -49,13 +63,12 @@ def penalty_env(grid, verts, pose, k, vals64=None):
     return term.sum(), np.concatenate([d_rho, d_omega]), d_verts
 
 
-def penalty_terms_abs(grid, verts, pose, k, vals64=None):
+def penalty_terms_abs(grid, verts, pose, k, vals64=None, sampler=None):
     """Sums of absolute per-vertex terms (scale for FP32 tolerances)."""
-    if vals64 is None:
-        vals64 = Q.grid_values_f64(grid.values, grid.dtype)
+    sampler = sampler or dense_sampler(grid, vals64)
     pose = np.asarray(pose, dtype=np.float64)
     xb = Q.transform(pose, verts)
-    term, phi, grad, act, _ = _terms(vals64, grid, xb, k)
+    term, phi, grad, act, _ = _terms(sampler, xb, k)
     w = np.where(act[:, None], k * np.where(act, phi, 0.0)[:, None] * grad, 0.0)
     return term.sum(), np.concatenate([np.abs(w).sum(0), np.abs(np.cross(xb, w)).sum(0)])
 
@@ -81,7 +94,7 @@ def _perturb(xb, i, s):
     return xb @ Rr.T, np.cross(e, xb)  # d x / d eps = e x x_B
 
 
-def fd_twist(grid, verts, pose, k, h=1e-6, vals64=None):
+def fd_twist(grid, verts, pose, k, h=1e-6, vals64=None, sampler=None):
     """Central differences of L_e over the 6 twist components.
 
     Returns (g_fd (6,), crossings (6,) int, bound (6,)).  ``crossings``
@@ -95,18 +108,17 @@ def fd_twist(grid, verts, pose, k, h=1e-6, vals64=None):
         most h k (|grad| |dx/d eps|)^2.
     ``bound`` is the sum of those shares.
     """
-    if vals64 is None:
-        vals64 = Q.grid_values_f64(grid.values, grid.dtype)
+    sampler = sampler or dense_sampler(grid, vals64)
     xb = Q.transform(pose, verts)
-    _, _, _, a0, _ = _terms(vals64, grid, xb, k)
+    _, _, _, a0, _ = _terms(sampler, xb, k)
     g = np.zeros(6)
     cross = np.zeros(6, dtype=np.int64)
     bound = np.zeros(6)
     for i in range(6):
         xp, dx = _perturb(xb, i, +h)
         xm, _ = _perturb(xb, i, -h)
-        tp, php, gp, ap, cp = _terms(vals64, grid, xp, k)
-        tm, phm, gm, am, cm = _terms(vals64, grid, xm, k)
+        tp, php, gp, ap, cp = _terms(sampler, xp, k)
+        tm, phm, gm, am, cm = _terms(sampler, xm, k)
         g[i] = (tp.sum() - tm.sum()) / (2.0 * h)
         dxn = np.linalg.norm(dx, axis=1)
         moved = np.any(cp != cm, axis=1) & (ap | am)
@@ -122,7 +134,7 @@ def fd_twist(grid, verts, pose, k, h=1e-6, vals64=None):
     return g, cross, bound
 
 
-def fd_verts(grid, verts, pose, k, h=1e-6, vals64=None):
+def fd_verts(grid, verts, pose, k, h=1e-6, vals64=None, sampler=None):
     """Central differences of L_e with respect to every vertex coordinate.
 
     Returns (g_fd (n,3), crossed (n,3) bool): a vertex coordinate is
@@ -130,18 +142,17 @@ def fd_verts(grid, verts, pose, k, h=1e-6, vals64=None):
     evaluations sit in different cells, or the vertex enters or leaves the
     penetrating set).
     """
-    if vals64 is None:
-        vals64 = Q.grid_values_f64(grid.values, grid.dtype)
+    sampler = sampler or dense_sampler(grid, vals64)
     pose = np.asarray(pose, dtype=np.float64)
     R = Q.rotation_from_quaternion(pose[:4])
     xb = Q.transform(pose, verts)
-    _, _, _, a0, _ = _terms(vals64, grid, xb, k)
+    _, _, _, a0, _ = _terms(sampler, xb, k)
     g = np.zeros((len(xb), 3))
     crossed = np.zeros((len(xb), 3), dtype=bool)
     for a in range(3):
         step = h * R[:, a]
-        tp, _, _, ap, cp = _terms(vals64, grid, xb + step, k)
-        tm, _, _, am, cm = _terms(vals64, grid, xb - step, k)
+        tp, _, _, ap, cp = _terms(sampler, xb + step, k)
+        tm, _, _, am, cm = _terms(sampler, xb - step, k)
         g[:, a] = (tp - tm) / (2.0 * h)
         crossed[:, a] = (np.any(cp != cm, axis=1) & (ap | am)) | (ap != am) | (ap != a0)
     return g, crossed

@@ -73,3 +73,15 @@ def sample_sparse(vals64, origin, h, dims, x, band):
     phi = np.where(inside, phi, np.nan)
     grad = np.where(inside[..., None], grad, 0.0)
     return phi, grad, inside, stored
+
+
+def sparse_sampler(vals64, origin, h, dims, band):
+    """x -> (phi, grad, inside, cell) of the sparse field above (the fine cell
+    is returned as the cell), for the penalty adjoint and its differences."""
+
+    def f(x):
+        phi, grad, inside, _ = sample_sparse(vals64, origin, h, dims, x, band)
+        _, cell, _ = Q.locate(x, origin, h, dims)
+        return phi, grad, inside, cell
+
+    return f

@@ -100,8 +100,8 @@ def reduce_highest_index(env, vidx, depth32, bins, cand, n_env, K):
 _orig_pen = OA.penalty_env
 
 
-def penalty_cross_sign(grid, verts, pose, k, vals64=None):
-    L, dxi, dv = _orig_pen(grid, verts, pose, k, vals64)
+def penalty_cross_sign(grid, verts, pose, k, vals64=None, sampler=None):
+    L, dxi, dv = _orig_pen(grid, verts, pose, k, vals64, sampler)
     dxi = dxi.copy()
     dxi[3:] = -dxi[3:]
     return L, dxi, dv

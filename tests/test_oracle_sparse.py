@@ -2,12 +2,17 @@
 against an explicit per-brick enumeration, an infinite band reproducing the
 dense interpolant, multilinear fields reproduced exactly by the coarse
 interpolant, a sphere within the coarse interpolation bound away from its
-band, and planted mistakes caught."""
+band, the penalty adjoint on the sparse field (an infinite band gives the
+dense adjoint; a half-space whose deep vertices take the coarse path gives
+the closed-form loss and gradients; analytic against central differences),
+and planted mistakes caught."""
 import itertools
 
 import numpy as np
 import pytest
+from scipy.spatial.transform import Rotation
 
+from oracle import adjoint as A
 from oracle import query as Q
 from oracle import sparse as OS
 from paper_2205_03532_amd import workloads as W
@@ -127,10 +132,92 @@ def test_sphere_within_coarse_bound_off_band():
     assert np.all(np.linalg.norm(gr[off][away], axis=1) > 0.8) and away.sum() > 2000
 
 
+# ------------------------------------------------------------ penalty adjoint on the sparse field
+
+
+def _sampler(g, band):
+    vals = Q.grid_values_f64(g.values, g.dtype)
+    return OS.sparse_sampler(vals, g.origin, g.h, g.dims, band)
+
+
+def test_sparse_penalty_infinite_band_is_the_dense_adjoint():
+    """Every brick stored: loss, twist gradient, vertex gradients and the
+    finite differences equal the dense oracle's, bit for bit."""
+    w = W.torus_workload(n_env=4)
+    g = w.grids[0]
+    verts = w.meshes[0].verts
+    sp = _sampler(g, np.inf)
+    for e in range(w.n_env):
+        L0, x0, v0 = A.penalty_env(g, verts, w.pose[:, e], 1e4)
+        L1, x1, v1 = A.penalty_env(g, verts, w.pose[:, e], 1e4, sampler=sp)
+        assert L0 == L1 and np.array_equal(x0, x1) and np.array_equal(v0, v1)
+    f0 = A.fd_twist(g, verts, w.pose[:, 0], 1e4)
+    f1 = A.fd_twist(g, verts, w.pose[:, 0], 1e4, sampler=sp)
+    assert all(np.array_equal(a, b) for a, b in zip(f0, f1))
+
+
+def test_sparse_penalty_halfspace_closed_form():
+    """phi = n.x - d sampled in FP64 with a 1.5-voxel band: the bricks deep
+    below the plane are not stored, yet the coarse interpolant of an affine
+    field is the field, so the penalty and its gradients are the half-space's
+    closed forms: L = sum 0.5 k phi^2, dL/drho = sum k phi n,
+    dL/domega = sum x_B x (k phi n), dL/dv = R^T (k phi n)."""
+    rng = np.random.default_rng(5)
+    nrm = np.array([0.3, -0.2, 0.9])
+    nrm /= np.linalg.norm(nrm)
+    d, k, h = 0.004, 1e4, 1e-3
+    g = sample_fp64(lambda p: p @ nrm - d, (31, 31, 31), (-0.015,) * 3, h)
+    band = 1.5 * h
+    dirs = rng.normal(size=(3000, 3))
+    verts = (dirs / np.linalg.norm(dirs, axis=1)[:, None] * 0.0125 * rng.uniform(0, 1, (3000, 1)) ** (1 / 3))
+    verts = verts.astype(np.float32)  # a ball that stays inside the grid under any rotation
+    pose = np.r_[W.shoemake_quat(rng, 1)[:, 0], [0.001, -0.001, 0.0]].astype(np.float32)
+    L, dxi, dv = A.penalty_env(g, verts, pose, k, sampler=_sampler(g, band))
+    q = pose[:4].astype(np.float64)
+    R = (q @ q) * Rotation.from_quat(q).as_matrix() + (1.0 - q @ q) * np.eye(3)
+    xb = verts.astype(np.float64) @ R.T + pose[4:].astype(np.float64)
+    phi = np.minimum(xb @ nrm - d, 0.0)
+    wv = k * phi[:, None] * nrm[None, :]
+    _, _, ins, stored = OS.sample_sparse(g.values, g.origin, g.h, g.dims, xb, band)
+    assert np.all(ins) and ((phi < 0) & ~stored).sum() > 300  # many penetrating vertices take the coarse path
+    scale = np.abs(wv).sum()
+    assert abs(L - np.sum(0.5 * k * phi ** 2)) <= 1e-12 * max(L, 1e-30) + 1e-15
+    assert np.allclose(dxi[:3], wv.sum(0), rtol=0, atol=1e-12 * scale)
+    assert np.allclose(dxi[3:], np.cross(xb, wv).sum(0), rtol=0, atol=1e-12 * scale)
+    assert np.allclose(dv, wv @ R, rtol=0, atol=1e-12 * np.abs(wv).max())
+
+
+def test_sparse_penalty_matches_finite_differences():
+    """A sphere with a 1.5-voxel band, vertices throughout the ball: the
+    analytic twist and vertex gradients of the sparse field against its own
+    central differences (h = 1e-7 m), within the kink bounds."""
+    g, c, r = sphere_grid(dims=(40, 40, 40), h=0.5e-3, r=7e-3)
+    band = np.float32(0.75e-3)
+    sp = _sampler(g, band)
+    rng = np.random.default_rng(3)
+    verts = (rng.uniform(-1, 1, (1500, 3)) * 6e-3).astype(np.float32)
+    checked_coarse = 0
+    for i in range(3):
+        pose = np.r_[W.shoemake_quat(rng, 1)[:, 0], c + rng.uniform(-1e-3, 1e-3, 3)].astype(np.float32)
+        L, dxi, dv = A.penalty_env(g, verts, pose, 1e4, sampler=sp)
+        gfd, cross, bound = A.fd_twist(g, verts, pose, 1e4, 1e-7, sampler=sp)
+        scale = max(np.max(np.abs(gfd)), 1e-12)
+        for j in range(6):
+            assert abs(dxi[j] - gfd[j]) <= 1e-5 * scale + 1e-9 + bound[j], (i, j, dxi[j], gfd[j], cross[j])
+        gv, crossed = A.fd_verts(g, verts, pose, 1e4, 1e-7, sampler=sp)
+        ok = ~crossed
+        assert np.allclose(dv[ok], gv[ok], rtol=1e-4, atol=1e-8 * scale)
+        xb = Q.transform(pose, verts)
+        _, _, ins, st = OS.sample_sparse(Q.grid_values_f64(g.values, g.dtype), g.origin, g.h, g.dims, xb, band)
+        checked_coarse += int((ins & ~st & np.all(ok, axis=1)).sum())
+    assert checked_coarse > 1000
+
+
 # ------------------------------------------------------------ planted mistakes
 
 SPARSE_PINS = [test_classification_matches_enumeration, test_infinite_band_is_the_dense_interpolant,
-               test_sphere_within_coarse_bound_off_band,
+               test_sphere_within_coarse_bound_off_band, test_sparse_penalty_halfspace_closed_form,
+               test_sparse_penalty_matches_finite_differences,
                lambda: test_multilinear_fields_are_exact_everywhere((0.3, -0.2, 0.5, 0.1, 0.0, 0.0, 0.0, 0.0))]
 
 
