@@ -94,7 +94,7 @@ def _perturb(xb, i, s):
     return xb @ Rr.T, np.cross(e, xb)  # d x / d eps = e x x_B
 
 
-def fd_twist(grid, verts, pose, k, h=1e-6, vals64=None, sampler=None):
+def fd_twist(grid, verts, pose, k, h=1e-6, vals64=None, sampler=None, jumps=False):
     """Central differences of L_e over the 6 twist components.
 
     Returns (g_fd (6,), crossings (6,) int, bound (6,)).  ``crossings``
@@ -107,10 +107,17 @@ def fd_twist(grid, verts, pose, k, h=1e-6, vals64=None, sampler=None):
         k |grad . dx/d eps|^2): the central difference is then off by at
         most h k (|grad| |dx/d eps|)^2.
     ``bound`` is the sum of those shares.
+
+    ``jumps``: the field may also jump in value across a cell face (the
+    narrow-band sparse grid does, between a stored brick and one that is
+    not); a vertex that changes cells then adds its whole difference
+    quotient and its whole analytic term, |(t+ - t-)/2h| + |w . dx/d eps|,
+    to the bound instead of the gradient-jump share.
     """
     sampler = sampler or dense_sampler(grid, vals64)
     xb = Q.transform(pose, verts)
-    _, _, _, a0, _ = _terms(sampler, xb, k)
+    _, phi0, grad0, a0, _ = _terms(sampler, xb, k)
+    w0 = np.where(a0[:, None], k * np.where(a0, phi0, 0.0)[:, None] * grad0, 0.0)
     g = np.zeros(6)
     cross = np.zeros(6, dtype=np.int64)
     bound = np.zeros(6)
@@ -124,7 +131,11 @@ def fd_twist(grid, verts, pose, k, h=1e-6, vals64=None, sampler=None):
         moved = np.any(cp != cm, axis=1) & (ap | am)
         flips = (ap != am) | (ap != a0)
         cross[i] = int((moved | flips).sum())
-        if moved.any():
+        if moved.any() and jumps:
+            fd_v = np.abs(tp[moved] - tm[moved]) / (2.0 * h)
+            an_v = np.abs(np.sum(w0[moved] * dx[moved], axis=1))
+            bound[i] += float(np.sum(fd_v + an_v))
+        elif moved.any():
             phi_abs = np.maximum(np.abs(np.nan_to_num(php[moved])), np.abs(np.nan_to_num(phm[moved])))
             jump = np.linalg.norm(gp[moved] - gm[moved], axis=1)
             bound[i] += float(np.sum(k * phi_abs * jump * dxn[moved]))

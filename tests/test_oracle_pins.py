@@ -386,6 +386,32 @@ def test_penalty_gradient_matches_finite_differences():
     assert checked >= 2
 
 
+def test_fd_bound_covers_a_value_jump():
+    """A field with a step: phi = z - z0 plus 1e-4 m where x > xs, cells of
+    1 mm.  One penetrating vertex straddles the step within the stencil of a
+    translation along x.  The central difference then carries the step
+    (|FD - analytic| = k |phi| 1e-4 / 2h, huge); the gradient-jump share
+    (no gradient jump here) does not cover it, the value-jump share of
+    jumps=True does, and the other components stay exact."""
+    xs, z0, k, h, step = 0.0, 0.01, 1e4, 1e-6, 1e-4
+
+    def sampler(x):
+        phi = x[:, 2] - z0 + np.where(x[:, 0] > xs, step, 0.0)
+        grad = np.tile([0.0, 0.0, 1.0], (len(x), 1))
+        cell = np.floor(x / 1e-3).astype(np.int64)
+        return phi, grad, np.ones(len(x), bool), cell
+
+    verts = np.array([[0.0, 0.0, 0.0], [0.0035, 0.0015, 0.0025], [-0.0045, 0.0025, 0.0015]], np.float32)
+    pose = np.array([0, 0, 0, 1, 0.0, 0.0, 0.0], np.float32)
+    L, dxi, _ = A.penalty_env(None, verts, pose, k, sampler=sampler)
+    g0, cross0, b0 = A.fd_twist(None, verts, pose, k, h, sampler=sampler)
+    g1, cross1, b1 = A.fd_twist(None, verts, pose, k, h, sampler=sampler, jumps=True)
+    assert np.array_equal(g0, g1) and np.array_equal(cross0, cross1)
+    assert cross0[0] == 1 and abs(dxi[0] - g0[0]) > 100 * max(b0[0], 1e-9)
+    assert abs(dxi[0] - g1[0]) <= b1[0]
+    assert np.allclose(dxi[1:3], g1[1:3], rtol=1e-9, atol=1e-9)
+
+
 # ---------------------------------------------------------------- half precision decode
 
 

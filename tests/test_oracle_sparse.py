@@ -190,7 +190,8 @@ def test_sparse_penalty_halfspace_closed_form():
 def test_sparse_penalty_matches_finite_differences():
     """A sphere with a 1.5-voxel band, vertices throughout the ball: the
     analytic twist and vertex gradients of the sparse field against its own
-    central differences (h = 1e-7 m), within the kink bounds."""
+    central differences (h = 1e-7 m), within the kink bounds (the field jumps
+    in value across a face between a stored brick and one that is not)."""
     g, c, r = sphere_grid(dims=(40, 40, 40), h=0.5e-3, r=7e-3)
     band = np.float32(0.75e-3)
     sp = _sampler(g, band)
@@ -200,7 +201,7 @@ def test_sparse_penalty_matches_finite_differences():
     for i in range(3):
         pose = np.r_[W.shoemake_quat(rng, 1)[:, 0], c + rng.uniform(-1e-3, 1e-3, 3)].astype(np.float32)
         L, dxi, dv = A.penalty_env(g, verts, pose, 1e4, sampler=sp)
-        gfd, cross, bound = A.fd_twist(g, verts, pose, 1e4, 1e-7, sampler=sp)
+        gfd, cross, bound = A.fd_twist(g, verts, pose, 1e4, 1e-7, sampler=sp, jumps=True)
         scale = max(np.max(np.abs(gfd)), 1e-12)
         for j in range(6):
             assert abs(dxi[j] - gfd[j]) <= 1e-5 * scale + 1e-9 + bound[j], (i, j, dxi[j], gfd[j], cross[j])
