@@ -7,7 +7,9 @@ import math
 
 import numpy as np
 
-from _gpu_common import ULP32, gradient_sensitivity, oracle_rows, position_error_voxels, to_np, torch_gpu
+import itertools
+
+from _gpu_common import FACE_BAND, ULP32, gradient_sensitivity, oracle_rows, position_error_voxels, to_np, torch_gpu
 from oracle import adjoint as OA
 from oracle import query as OQ
 from paper_2205_03532_amd import fc
@@ -15,7 +17,60 @@ from paper_2205_03532_amd import fc
 KP = 1e4
 
 
-def adjoint_bounds(w, envs, k, o=None, S=None, cmax=None, extra_ulps=0.0):
+def face_slack(w, o, k, sampler_of=None):
+    """Per-row allowances for points within the FP32 position error of a cell
+    face: the kernel may take the cell on either side, where the trilinear
+    field's gradient jumps (and a sparse field's value may jump too).  The
+    point is nudged across every near face (all sign combinations of the
+    near axes) and the whole difference of its loss term, w = k phi grad and
+    moment x_B x w between the sides is allowed.  ``sampler_of(e)`` gives
+    env e's field (default: the dense interpolant of its grid)."""
+    n = len(o["phi"])
+    out = {key: np.zeros(n) for key in ("loss", "w", "mom")}
+    du = np.max(position_error_voxels(o), axis=1)
+    band = np.maximum(FACE_BAND, 2.0 * du)[:, None]
+    t = o["u"] - np.floor(o["u"])
+    near = ((t < band) | (t > 1.0 - band)) & o["inside"][:, None]
+    idx = np.nonzero(near.any(axis=1))[0]
+    if not len(idx):
+        return out
+
+    def terms(phi, grad):
+        act = np.isfinite(phi) & (np.nan_to_num(phi, nan=1.0) < 0)
+        p = np.where(act, phi, 0.0)
+        return 0.5 * k * p ** 2, k * p[:, None] * np.where(act[:, None], grad, 0.0)
+
+    t0, w0 = terms(o["phi"][idx], o["grad"][idx])
+    x0 = o["x_b"][idx]
+    h = o["h"][idx][:, None]
+    env = o["env"][idx]
+    samplers, dense = {}, {}
+    for e in np.unique(env):
+        if sampler_of is not None:
+            samplers[e] = sampler_of(int(e))
+        else:
+            gi = int(w.env_grid[e])
+            if gi not in dense:
+                dense[gi] = OA.dense_sampler(w.grids[gi])
+            samplers[e] = dense[gi]
+    for sgn in itertools.product((-1.0, 0.0, 1.0), repeat=3):
+        step = np.asarray(sgn)[None, :] * near[idx] * (2.0 * band[idx] * h)
+        if not step.any():
+            continue
+        phi = np.full(len(idx), np.nan)
+        grad = np.zeros((len(idx), 3))
+        for e in np.unique(env):
+            sel = env == e
+            phi[sel], grad[sel], _, _ = samplers[e](x0[sel] + step[sel])
+        t1, w1 = terms(phi, grad)
+        dw = np.linalg.norm(w1 - w0, axis=1)
+        out["loss"][idx] = np.maximum(out["loss"][idx], np.abs(t1 - t0))
+        out["w"][idx] = np.maximum(out["w"][idx], dw)
+        out["mom"][idx] = np.maximum(out["mom"][idx], np.linalg.norm(x0, axis=1) * dw)
+    return out
+
+
+def adjoint_bounds(w, envs, k, o=None, S=None, cmax=None, extra_ulps=0.0, row_slack=None, sampler_of=None):
     """FP32 error bounds of the adjoint per env, from the oracle's per-vertex data.
 
     Per vertex: dx <= position rounding (m); dphi <= |g| dx + 4 ulp(cmax) (lerp
@@ -28,6 +83,8 @@ def adjoint_bounds(w, envs, k, o=None, S=None, cmax=None, extra_ulps=0.0):
     ``cmax`` the cell data of gradient_sensitivity (e.g. corners the kernel
     synthesises), ``extra_ulps`` adds that many ulps of cmax to the corner
     rounding (for corners that are themselves computed in FP32).
+    ``row_slack`` adds per-row allowances {"loss", "w", "mom"}; the rows near a
+    cell face always get face_slack's (with ``sampler_of`` as the field).
     """
     o = oracle_rows(w, envs) if o is None else o
     du = np.max(position_error_voxels(o), axis=1)
@@ -48,6 +105,12 @@ def adjoint_bounds(w, envs, k, o=None, S=None, cmax=None, extra_ulps=0.0):
     dloss = np.where(act, k * np.abs(phi) * dphi + 2 * ULP32 * 0.5 * k * phi ** 2, 0.0)
     dloss = np.where(near0, 0.5 * k * (np.abs(phi) + dphi) ** 2, dloss)
     dmom = np.where(act | near0, xb * dw + wabs * dx + 3 * ULP32 * xb * wabs, 0.0)
+    fs = face_slack(w, o, k, sampler_of)
+    dloss, dw, dmom = dloss + fs["loss"], dw + fs["w"], dmom + fs["mom"]
+    if row_slack is not None:
+        dloss = dloss + row_slack["loss"]
+        dw = dw + row_slack["w"]
+        dmom = dmom + row_slack["mom"]
     out = {}
     for e in envs:
         sel = o["env"] == e
@@ -95,7 +158,11 @@ def check_vs_oracle(w, res, envs, per_env, penalty=None, bounds=None):
         worst = max(worst, np.max(np.abs(res["d_pose"][:, e] - dxi)) / (2 * max(b["rho"], b["omega"]) + slack))
         if per_env:
             gv = res["d_verts"].reshape(3, -1)[:, off[e]:off[e + 1]].T
-            assert np.all(np.abs(gv - dv) <= 2 * b["verts"][:, None] + 1e-9), e
+            err = np.abs(gv - dv)
+            tolv = 2 * b["verts"][:, None] + 1e-9
+            if not np.all(err <= tolv):
+                r = int(np.argmax(np.max(err / tolv, axis=1)))
+                raise AssertionError(f"env {e} vertex {r}: gpu {gv[r]} oracle {dv[r]} bound {tolv[r, 0]:.3e}")
         shared[mi] += dv
         shared_tol[mi] += 2 * b["verts"]
     return shared, shared_tol, worst

@@ -1,63 +1,15 @@
 """GPU parity of the penetration-penalty adjoint (loss, twist and vertex
 gradients) against the FP64 oracle and FP64 finite differences, plus the
 autograd wrapper and graph replay."""
-import math
-
 import numpy as np
 import pytest
 
-from _gpu_common import (ULP32, assert_same, gradient_sensitivity, oracle_rows, position_error_voxels, to_np,
-                         torch_gpu)
-from oracle import adjoint as OA
-from oracle import query as OQ
+from _adjoint_common import KP, check_fd, check_vs_oracle, run_backward, shared_blocks
+from _gpu_common import assert_same, to_np, torch_gpu
 from paper_2205_03532_amd import fc
 from paper_2205_03532_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-KP = 1e4
-
-
-def adjoint_bounds(w, envs, k):
-    """FP32 error bounds of the adjoint per env, from the oracle's per-vertex data.
-
-    Per vertex: dx <= position rounding (m); dphi <= |g| dx + 4 ulp(cmax) (lerp
-    rounding); dgrad <= (sqrt(3) S du + 8 ulp cmax) / h; for a penetrating
-    vertex dw <= k (dphi |g| + |phi| dgrad) + 3 ulp |w|.  A vertex with
-    |phi| <= dphi may be penetrating on one side only: its whole term,
-    k (|phi| + dphi)(|g| + dgrad), is allowed.
-    """
-    o = oracle_rows(w, envs)
-    du = np.max(position_error_voxels(o), axis=1)
-    dx = du * o["h"]
-    S, cmax = gradient_sensitivity(w, o)
-    g = np.linalg.norm(o["grad"], axis=1)
-    phi_all = np.nan_to_num(o["phi"], nan=1.0)
-    act = o["inside"] & (phi_all < 0)
-    dphi = g * dx + 4 * ULP32 * cmax
-    near0 = o["inside"] & (np.abs(phi_all) <= dphi)
-    phi = np.where(act | near0, phi_all, 0.0)
-    dgrad = (math.sqrt(3) * S * du + 8 * ULP32 * cmax) / o["h"]
-    wabs = k * np.abs(phi) * g
-    dw = np.where(act, k * (dphi * g + np.abs(phi) * dgrad) + 3 * ULP32 * wabs, 0.0)
-    dw = np.where(near0, k * (np.abs(phi) + dphi) * (g + dgrad), dw)
-    xb = np.linalg.norm(o["x_b"], axis=1)
-    dloss = np.where(act, k * np.abs(phi) * dphi + 2 * ULP32 * 0.5 * k * phi ** 2, 0.0)
-    dloss = np.where(near0, 0.5 * k * (np.abs(phi) + dphi) ** 2, dloss)
-    dmom = np.where(act | near0, xb * dw + wabs * dx + 3 * ULP32 * xb * wabs, 0.0)
-    out = {}
-    for e in envs:
-        sel = o["env"] == e
-        out[e] = dict(loss=dloss[sel].sum(), rho=dw[sel].sum(), omega=dmom[sel].sum(), verts=dw[sel],
-                      abs_terms=(0.5 * k * phi[sel] ** 2).sum() + wabs[sel].sum() * (1 + xb[sel].max()))
-    return out
-
-
-def run_backward(batch, pose, per_env, upstream=None):
-    torch = torch_gpu()
-    g = batch.new_grads(per_env=per_env)
-    fc.fc_sdf_query_backward(batch, pose, KP, g, upstream=upstream)
-    torch.cuda.synchronize()
-    return to_np({k: v for k, v in g.items() if k != "per_env"})
 
 
 @pytest.fixture(scope="module")
@@ -74,35 +26,10 @@ def nutbolt40():
     return w, fc.Batch.from_workload(w), fc.pose_tensor(w.pose)
 
 
-def _check_vs_oracle(w, res, envs, per_env):
-    bounds = adjoint_bounds(w, envs, KP)
-    off = w.env_query_offsets()
-    g = w.grids[0]
-    vals = OQ.grid_values_f64(g.values, g.dtype)
-    shared = np.zeros((w.meshes[0].n, 3))
-    shared_tol = np.zeros(w.meshes[0].n)
-    worst = 0.0
-    for e in envs:
-        L, dxi, dv = OA.penalty_env(g, w.meshes[0].verts, w.pose[:, e], KP, vals)
-        b = bounds[e]
-        slack = 1e-6 * b["abs_terms"] + 1e-12
-        assert abs(res["loss"][e] - L) <= 2 * b["loss"] + slack, (e, res["loss"][e], L, b["loss"])
-        for i in range(3):
-            assert abs(res["d_pose"][i, e] - dxi[i]) <= 2 * b["rho"] + slack, (e, i)
-            assert abs(res["d_pose"][3 + i, e] - dxi[3 + i]) <= 2 * b["omega"] + slack, (e, 3 + i)
-        worst = max(worst, np.max(np.abs(res["d_pose"][:, e] - dxi)) / (2 * max(b["rho"], b["omega"]) + slack))
-        if per_env:
-            gv = res["d_verts"].reshape(3, -1)[:, off[e]:off[e + 1]].T
-            assert np.all(np.abs(gv - dv) <= 2 * b["verts"][:, None] + 1e-9), e
-        shared += dv
-        shared_tol += 2 * b["verts"]
-    return shared, shared_tol, worst
-
-
 def test_torus_adjoint_matches_oracle(torus16):
     w, b, pose = torus16
     res = run_backward(b, pose, per_env=True)
-    _, _, worst = _check_vs_oracle(w, res, range(w.n_env), True)
+    _, _, worst = check_vs_oracle(w, res, range(w.n_env), True)
     print("torus adjoint: worst |err|/bound =", worst)
     assert res["loss"].max() > 0
 
@@ -110,11 +37,11 @@ def test_torus_adjoint_matches_oracle(torus16):
 def test_nutbolt_adjoint_matches_oracle_and_shared_sum(nutbolt40):
     w, b, pose = nutbolt40
     res_env = run_backward(b, pose, per_env=True)
-    shared, tol, worst = _check_vs_oracle(w, res_env, range(w.n_env), True)
+    shared, tol, worst = check_vs_oracle(w, res_env, range(w.n_env), True)
     print("nut-bolt adjoint: worst |err|/bound =", worst)
     res = run_backward(b, pose, per_env=False)
-    gv = res["d_verts"].reshape(3, -1).T
-    assert np.all(np.abs(gv - shared) <= tol[:, None] + 1e-6 * np.abs(shared) + 1e-9)
+    gv = shared_blocks(w, res["d_verts"])[0]
+    assert np.all(np.abs(gv - shared[0]) <= tol[0][:, None] + 1e-6 * np.abs(shared[0]) + 1e-9)
     # loss / pose outputs do not depend on the vertex-gradient mode
     assert_same(dict(l=res["loss"], p=res["d_pose"]), dict(l=res_env["loss"], p=res_env["d_pose"]))
 
@@ -174,26 +101,7 @@ def test_gradients_match_fp64_finite_differences():
     sub = W.subset(w, envs)
     b = fc.Batch.from_workload(sub)
     res = run_backward(b, fc.pose_tensor(sub.pose), per_env=True)
-    g = sub.grids[0]
-    vals = OQ.grid_values_f64(g.values, g.dtype)
-    bounds = adjoint_bounds(sub, range(sub.n_env), KP)
-    n_kinked = n_smooth = 0
-    off = sub.env_query_offsets()
-    for e in range(sub.n_env):
-        gfd, cross, kb = OA.fd_twist(g, sub.meshes[0].verts, sub.pose[:, e], KP, 1e-6, vals)
-        ref = np.max(np.abs(gfd))
-        for i in range(6):
-            fp32 = 2 * (bounds[e]["rho"] if i < 3 else bounds[e]["omega"])
-            tol = 1e-3 * max(abs(gfd[i]), 1e-3 * ref) + kb[i] + fp32 + 1e-9
-            assert abs(res["d_pose"][i, e] - gfd[i]) <= tol, (e, i, res["d_pose"][i, e], gfd[i], cross[i], kb[i])
-            n_kinked += int(cross[i] > 0)
-            n_smooth += int(cross[i] == 0)
-        # vertex gradients: smooth coordinates only (each vertex's own term)
-        gv, crossed = OA.fd_verts(g, sub.meshes[0].verts, sub.pose[:, e], KP, 1e-6, vals)
-        dv = res["d_verts"].reshape(3, -1)[:, off[e]:off[e + 1]].T
-        ok = ~crossed
-        tolv = 1e-3 * np.abs(gv) + 2 * bounds[e]["verts"][:, None] + 1e-7
-        assert np.all(np.abs(dv - gv)[ok] <= tolv[ok]), e
+    n_smooth, n_kinked = check_fd(sub, res, range(sub.n_env))
     print(f"FD components: {n_smooth} smooth, {n_kinked} with kinks (checked within their bound)")
 
 
