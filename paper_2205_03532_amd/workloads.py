@@ -664,6 +664,24 @@ def torus_workload(seed=1000, n_env=256, K=16, level=4) -> Workload:
                     meta=dict(seed=seed, gen=GEN_VERSION))
 
 
+def torus_tube_workload(seed=1005, n_env=32, K=16) -> Workload:
+    """The torus grid above with a small icosphere (r = 3 mm, 642 vertices)
+    inside its tube: centres on the tube's core circle (R = 2 cm) jittered by
+    +-1 mm, uniform random rotations.  Every vertex penetrates, 1-3 mm deep,
+    so with a narrow band of 1.5 mm many fall in bricks of the sparse grid
+    that are not stored."""
+    rng = np.random.default_rng(seed)
+    g = sample_grid(lambda p: field_torus(p, 0.02, 0.005), (64, 64, 64), (-0.0315,) * 3, 1e-3)
+    m = icosphere(3, 0.003)
+    a = rng.uniform(0.0, 2.0 * math.pi, n_env)
+    t = np.stack([0.02 * np.cos(a), 0.02 * np.sin(a), np.zeros(n_env)]) + rng.uniform(-1e-3, 1e-3, (3, n_env))
+    q = shoemake_quat(rng, n_env)
+    return Workload(name="torus64-tube-icosphere", grids=[g], meshes=[m],
+                    env_grid=np.zeros(n_env, np.int32), env_mesh=np.zeros(n_env, np.int32),
+                    pose=pack_pose(q, t), bins=fibonacci_bins(K), margin=0.0,
+                    meta=dict(seed=seed, gen=GEN_VERSION))
+
+
 def nut_bolt_workload(seed=1001, n_env=1000, K=32, spec: NutBoltSpec = M16_BOLT_256x256x512) -> Workload:
     """n_env nuts threaded onto one shared bolt grid (one SDF, one mesh)."""
     rng = np.random.default_rng(seed)

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from _gpu_common import (DEPTH_TOL_F32, FACE_BAND, assert_same, check_bins_exact, check_reduction_exact,
-                         oracle_rows, position_error_voxels, rows_of, to_np, torch_gpu)
+                         gradient_sensitivity, oracle_rows, position_error_voxels, rows_of, to_np, torch_gpu)
 from oracle import query as OQ
 from oracle import sparse as OS
 from paper_2205_03532_amd import fc
@@ -226,3 +226,72 @@ def test_sparse_graph_replay_and_autograd():
             mt.grad = None
     for a_, b_ in zip(grads[0], grads[1]):
         assert np.array_equal(a_.view(np.uint32), b_.view(np.uint32))
+
+
+def _sparse_cell_data(w, o, band):
+    """Per row, S (largest mixed second difference) and cmax (scale of the
+    FP32 rounding) of the corners the kernel interpolates: a stored brick's
+    dense cell corners; in a brick that is not stored, S of the coarse
+    interpolant at the fine cell's 8 corners and cmax of the brick's 8
+    corner nodes, from which the kernel expands those corners in FP32."""
+    import itertools
+
+    S, cmax = gradient_sensitivity(w, o)
+    g = w.grids[0]
+    vals = OQ.grid_values_f64(g.values, g.dtype)
+    idx = np.nonzero(o["inside"] & ~o["stored"])[0]
+    cell = o["cell"][idx]
+    C = {}
+    for a, b, c in itertools.product((0, 1), repeat=3):
+        t = np.tile(np.array([a, b, c], np.float64), (len(idx), 1))
+        C[a, b, c], _ = OS.coarse_interpolant(vals, cell, t, g.h)
+    m = np.zeros(len(idx))
+    for k in (0, 1):
+        m = np.maximum(m, np.abs(C[1, 1, k] - C[1, 0, k] - C[0, 1, k] + C[0, 0, k]))
+        m = np.maximum(m, np.abs(C[1, k, 1] - C[1, k, 0] - C[0, k, 1] + C[0, k, 0]))
+        m = np.maximum(m, np.abs(C[k, 1, 1] - C[k, 1, 0] - C[k, 0, 1] + C[k, 0, 0]))
+    b0 = 3 * (cell // 3)
+    cm = np.zeros(len(idx))
+    for a, b, c in itertools.product((0, 3), repeat=3):
+        cm = np.maximum(cm, np.abs(vals[b0[:, 2] + c, b0[:, 1] + b, b0[:, 0] + a]))
+    S[idx], cmax[idx] = m, cm
+    return S, cmax
+
+
+def test_sparse_coarse_adjoint_matches_oracle_and_fd():
+    """A small icosphere inside the torus's tube with a 1.5-voxel band: its
+    vertices penetrate 1-3 mm, many in bricks that are not stored, so loss,
+    twist and vertex gradients come partly from the coarse interpolant.
+    Per-env mode against the FP64 oracle on the sparse field, the shared mode
+    against the oracle's sum, and FP64 central differences of that field
+    (which jumps in value across faces between stored and unstored bricks)."""
+    from _adjoint_common import KP, adjoint_bounds, check_fd, check_vs_oracle, run_backward, shared_blocks
+    from oracle import adjoint as OA
+
+    torch_gpu()
+    w = W.torus_tube_workload()
+    g, verts = w.grids[0], w.meshes[0].verts
+    envs = list(range(w.n_env))
+    band = float(np.float32(1.5 * g.h))
+    b = fc.Batch.from_workload(w, layout="sparse", band=band)
+    pose = fc.pose_tensor(w.pose)
+    res = run_backward(b, pose, per_env=True)
+    o = sparse_oracle(w, envs, band)
+    pen = o["inside"] & (o["phi"] < 0)
+    n_coarse, n_stored = int((pen & ~o["stored"]).sum()), int((pen & o["stored"]).sum())
+    assert n_coarse > 1000 and n_stored > 1000, (n_coarse, n_stored)
+    S, cmax = _sparse_cell_data(w, o, band)
+    vals = OQ.grid_values_f64(g.values, g.dtype)
+    smp = OS.sparse_sampler(vals, g.origin, g.h, g.dims, band)
+    # rows near a cell face (brick faces among them, where the field jumps
+    # between a stored brick and one that is not) are allowed either side
+    bounds = adjoint_bounds(w, envs, KP, o=o, S=S, cmax=cmax, extra_ulps=40.0, sampler_of=lambda e: smp)
+    shared, tol, worst = check_vs_oracle(w, res, envs, True, bounds=bounds,
+                                         penalty=lambda e: OA.penalty_env(g, verts, w.pose[:, e], KP, sampler=smp))
+    res_sh = run_backward(b, pose, per_env=False)
+    gv = shared_blocks(w, res_sh["d_verts"])[0]
+    assert np.all(np.abs(gv - shared[0]) <= tol[0][:, None] + 1e-6 * np.abs(shared[0]) + 1e-9)
+    n_smooth, n_kinked = check_fd(w, res, envs, bounds=bounds, sampler_of=lambda e: smp, jumps=True)
+    print(f"sparse adjoint: {n_coarse} penetrating vertices in coarse bricks, {n_stored} in stored; "
+          f"worst twist |err|/bound {worst:.3f}; FD {n_smooth} smooth, {n_kinked} kinked components")
+    assert n_smooth > 0
