@@ -256,6 +256,7 @@ fc_status fc_workspace_init(const fc_batch* batch, void* ws, size_t ws_bytes, vo
 fc_status fc_sdf_query(const fc_batch* batch, const float* pose, const fc_candidates* cand,
                        const fc_contacts* fused_out, void* ws, size_t ws_bytes, void* stream);
 
+
 /* FindDeepest / BinReduce over candidates written by fc_sdf_query with the
  * same batch and pose: per (env, bin) the candidate of greatest depth, equal
  * depths to the lowest vertex index.  The winner's point is recomputed from
@@ -450,6 +451,15 @@ fc_status fc_bake_table(const float* verts, int32_t n_verts, const int32_t* tris
  * the data of a linear FC_F32 fc_grid with the same nx, ny, nz, origin, h. */
 fc_status fc_bake_sdf(const void* table, int32_t n_tris, int32_t nx, int32_t ny, int32_t nz, const float* origin,
                       float h, float* out, void* stream);
+
+/* The same bake with culling off: every node is evaluated against every
+ * triangle, in the same arithmetic, so the result is the definition above
+ * evaluated exhaustively.  Same arguments, errors and output as fc_bake_sdf;
+ * the cost grows as nodes x triangles.  Its purpose is verification: for a
+ * given mesh and grid, fc_bake_sdf's output must equal this one's bit for
+ * bit (the culling discards only triangles that cannot win or tie). */
+fc_status fc_bake_sdf_unculled(const void* table, int32_t n_tris, int32_t nx, int32_t ny, int32_t nz,
+                               const float* origin, float h, float* out, void* stream);
 
 /* ---- autotuning and diagnostics ----------------------------------------- */
 

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <limits>
 #include <mutex>
 #include <algorithm>
 #include <string>
@@ -1370,8 +1371,15 @@ fc_status fc_bake_table(const float* verts, int32_t n_verts, const int32_t* tris
   return build_bake_table(verts, n_verts, tris, n_tris, (float4*)table);
 }
 
-fc_status fc_bake_sdf(const void* table, int32_t n_tris, int32_t nx, int32_t ny, int32_t nz, const float* origin,
-                      float h, float* out, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Both bake calls: validation, the kernel's arguments, the launch.  With cull
+// off the slack is infinite, so every cluster and triangle bound passes and
+// the kernel evaluates every (node, triangle) pair.
+fc_status bake_sdf(const void* table, int32_t n_tris, int32_t nx, int32_t ny, int32_t nz, const float* origin,
+                   float h, float* out, void* stream, bool cull) {
   if (!table || !origin || !out) return FC_ERR_NULL;
   if (n_tris < 4 || n_tris > kBakeMaxTris) return FC_ERR_SHAPE;
   if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz >= (1LL << 31)) return FC_ERR_SHAPE;
@@ -1402,10 +1410,24 @@ fc_status fc_bake_sdf(const void* table, int32_t n_tris, int32_t nx, int32_t ny,
   const int n[3] = {nx, ny, nz};
   for (int a = 0; a < 3; ++a)
     L = std::max({L, std::fabs((double)origin[a]), std::fabs((double)origin[a] + (double)h * (n[a] - 1))});
-  b.slack = (float)(L * 0x1p-12);
+  b.slack = cull ? (float)(L * 0x1p-12) : std::numeric_limits<float>::infinity();
   b.out = out;
   FC_HIP(launch_bake(b, (hipStream_t)stream));
   return FC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fc_status fc_bake_sdf(const void* table, int32_t n_tris, int32_t nx, int32_t ny, int32_t nz, const float* origin,
+                      float h, float* out, void* stream) {
+  return bake_sdf(table, n_tris, nx, ny, nz, origin, h, out, stream, true);
+}
+
+fc_status fc_bake_sdf_unculled(const void* table, int32_t n_tris, int32_t nx, int32_t ny, int32_t nz,
+                               const float* origin, float h, float* out, void* stream) {
+  return bake_sdf(table, n_tris, nx, ny, nz, origin, h, out, stream, false);
 }
 
 int32_t fc_autotune_load(const char* path) {

@@ -126,6 +126,8 @@ SIGNATURES = {
     "fc_bake_table": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "fc_bake_sdf": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float),
                               C.c_float, C.c_void_p, C.c_void_p]),
+    "fc_bake_sdf_unculled": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float),
+                                       C.c_float, C.c_void_p, C.c_void_p]),
     "fc_status_str": (C.c_char_p, [C.c_int]),
     "fc_last_hip_error": (C.c_int32, []),
     "fc_version": (C.c_char_p, []),
@@ -176,6 +178,82 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+# ---- argument checks: the C ABI receives bare device pointers and cannot
+# check what they point at, so every wrapper checks each tensor's device,
+# dtype, shape and contiguity against the batch before the call.
+def _need(t, what, dtype, shape, device):
+    import torch
+
+    if t is None:
+        raise ValueError(f"{what} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch.Tensor, not {type(t).__name__}")
+    if t.device != device:
+        raise ValueError(f"{what} must be on {device}, not {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, not {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+def _check_pose(batch, pose):
+    import torch
+
+    _need(pose, "pose", torch.float32, (7, batch.n_env), batch.device)
+
+
+def _check_candidates(batch, cand, faces=False):
+    import torch
+
+    Q = max(batch.Qf, 1) if faces else batch.Q
+    d = batch.device
+    _need(cand["phi"], "cand['phi']", torch.float32, (Q,), d)
+    _need(cand["normal"], "cand['normal']", torch.float32, (3, Q), d)
+    _need(cand["bin"], "cand['bin']", torch.int16, (Q,), d)
+    if faces or cand.get("point") is not None:
+        _need(cand.get("point"), "cand['point']", torch.float32, (3, Q), d)
+
+
+def _check_contacts(batch, out):
+    import torch
+
+    S, d = batch.n_env * batch.K, batch.device
+    _need(out["vidx"], "contacts['vidx']", torch.int32, (S,), d)
+    _need(out["depth"], "contacts['depth']", torch.float32, (S,), d)
+    _need(out["point"], "contacts['point']", torch.float32, (3, S), d)
+    _need(out["normal"], "contacts['normal']", torch.float32, (3, S), d)
+    _need(out["count"], "contacts['count']", torch.int32, (batch.n_env,), d)
+
+
+def _check_grads(batch, grads, upstream):
+    import torch
+
+    d, n = batch.device, batch.n_env
+    nv = batch.Q if grads.get("per_env") else sum(batch.mesh_sizes)
+    if grads.get("loss") is not None:
+        _need(grads["loss"], "grads['loss']", torch.float32, (n,), d)
+    if grads.get("d_pose") is not None:
+        _need(grads["d_pose"], "grads['d_pose']", torch.float32, (6, n), d)
+    if grads.get("d_verts") is not None:
+        _need(grads["d_verts"], "grads['d_verts']", torch.float32, (3 * nv,), d)
+    if upstream is not None:
+        _need(upstream, "upstream", torch.float32, (n,), d)
+
+
+def _check_patches(batch, out, max_patches):
+    import torch
+
+    S, d = batch.n_env * int(max_patches), batch.device
+    _need(out["count"], "patches['count']", torch.int32, (batch.n_env,), d)
+    for k in ("founder", "vidx", "members"):
+        _need(out[k], f"patches['{k}']", torch.int32, (S,), d)
+    _need(out["depth"], "patches['depth']", torch.float32, (S,), d)
+    for k in ("normal", "point"):
+        _need(out[k], f"patches['{k}']", torch.float32, (3, S), d)
+
+
 class Batch:
     """A batch of environments resident on one GPU.
 
@@ -188,7 +266,10 @@ class Batch:
         import torch
 
         L = lib()
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         self.n_env = int(len(env_grid))
         self.K = int(bins.shape[1])
         self._keep = []
@@ -388,6 +469,11 @@ def _byref(s):
 
 
 def fc_sdf_query(batch: Batch, pose, cand=None, fused_out=None, stream=None):
+    _check_pose(batch, pose)
+    if cand is not None:
+        _check_candidates(batch, cand)
+    if fused_out is not None:
+        _check_contacts(batch, fused_out)
     cs, os_ = _cand_struct(cand), _contacts_struct(fused_out)
     _check(lib().fc_sdf_query(batch.handle, _ptr(pose), _byref(cs), _byref(os_),
                               C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes, _stream(stream)),
@@ -395,18 +481,26 @@ def fc_sdf_query(batch: Batch, pose, cand=None, fused_out=None, stream=None):
 
 
 def fc_contact_reduce(batch: Batch, pose, cand, out, stream=None):
+    _check_pose(batch, pose)
+    _check_candidates(batch, cand)
+    _check_contacts(batch, out)
     _check(lib().fc_contact_reduce(batch.handle, _ptr(pose), C.byref(_cand_struct(cand)),
                                    C.byref(_contacts_struct(out)), C.c_void_p(batch.workspace.data_ptr()),
                                    batch.ws_bytes, _stream(stream)), "fc_contact_reduce")
 
 
 def fc_sdf_query_backward(batch: Batch, pose, k, grads, upstream=None, stream=None):
+    _check_pose(batch, pose)
+    _check_grads(batch, grads, upstream)
     _check(lib().fc_sdf_query_backward(batch.handle, _ptr(pose), float(k), _ptr(upstream),
                                        C.byref(_grads_struct(grads)), C.c_void_p(batch.workspace.data_ptr()),
                                        batch.ws_bytes, _stream(stream)), "fc_sdf_query_backward")
 
 
 def fc_sdf_query_and_backward(batch: Batch, pose, fused_out, k, grads, upstream=None, stream=None):
+    _check_pose(batch, pose)
+    _check_contacts(batch, fused_out)
+    _check_grads(batch, grads, upstream)
     _check(lib().fc_sdf_query_and_backward(batch.handle, _ptr(pose), C.byref(_contacts_struct(fused_out)), float(k),
                                            _ptr(upstream), C.byref(_grads_struct(grads)),
                                            C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes,
@@ -418,6 +512,11 @@ PGD_ITERS, PGD_STEP0 = 8, 0.5  # per-face descent defaults (trials, first step i
 
 def fc_sdf_query_faces(batch: Batch, pose, cand=None, fused_out=None, iters=PGD_ITERS, step0=PGD_STEP0,
                        stream=None):
+    _check_pose(batch, pose)
+    if cand is not None:
+        _check_candidates(batch, cand, faces=True)
+    if fused_out is not None:
+        _check_contacts(batch, fused_out)
     cs, os_ = _cand_struct(cand), _contacts_struct(fused_out)
     p = fc_pgd(int(iters), float(step0))
     _check(lib().fc_sdf_query_faces(batch.handle, _ptr(pose), C.byref(p), _byref(cs), _byref(os_),
@@ -428,6 +527,8 @@ def fc_sdf_query_faces(batch: Batch, pose, cand=None, fused_out=None, iters=PGD_
 def fc_contact_patches(batch: Batch, pose, out, max_patches=PATCH_MAX, cos_sim=PATCH_COS, stream=None):
     """Patch reduction (Algorithm 1) of every environment into ``out``
     (Batch.new_patches(max_patches))."""
+    _check_pose(batch, pose)
+    _check_patches(batch, out, max_patches)
     prm = fc_patch_params(int(max_patches), float(cos_sim))
     ps = fc_patches(*[_ptr(out[k]) for k in ("count", "founder", "normal", "vidx", "depth", "point", "members")])
     _check(lib().fc_contact_patches(batch.handle, _ptr(pose), C.byref(prm), C.byref(ps), _stream(stream)),
@@ -436,6 +537,10 @@ def fc_contact_patches(batch: Batch, pose, out, max_patches=PATCH_MAX, cos_sim=P
 
 def fc_gather_probe(batch: Batch, pose, sink, stream=None):
     """The one-pass kernel's loads without its arithmetic (a measurement aid)."""
+    import torch
+
+    _check_pose(batch, pose)
+    _need(sink, "sink", torch.float32, tuple(sink.shape), batch.device)
     _check(lib().fc_gather_probe(batch.handle, _ptr(pose), _ptr(sink), _stream(stream)), "fc_gather_probe")
 
 
@@ -464,19 +569,22 @@ class BakeTable:
         self.table = torch.from_numpy(fc_bake_table(verts, tris)).to(device)
 
 
-def fc_bake_sdf(table: BakeTable, dims, origin, h, out=None, stream=None):
+def fc_bake_sdf(table: BakeTable, dims, origin, h, out=None, stream=None, cull=True):
     """Signed distance of the table's mesh at every node: a float32 tensor
-    [nz][ny][nx] (``out`` if given)."""
+    [nz][ny][nx] (``out`` if given).  ``cull=False`` calls
+    fc_bake_sdf_unculled (every node against every triangle)."""
     import torch
 
     nx, ny, nz = (int(d) for d in dims)
     if out is None:
         out = torch.empty((nz, ny, nx), dtype=torch.float32, device=table.table.device)
-    elif out.dtype != torch.float32 or out.numel() != nx * ny * nz or not out.is_contiguous():
+    elif (out.dtype != torch.float32 or out.numel() != nx * ny * nz or not out.is_contiguous()
+          or out.device != table.table.device):
         raise ValueError("out must be a contiguous float32 tensor of nx*ny*nz elements")
     o = (C.c_float * 3)(*[float(x) for x in origin])
-    _check(lib().fc_bake_sdf(_ptr(table.table), table.n_tris, nx, ny, nz, o, float(h), _ptr(out), _stream(stream)),
-           "fc_bake_sdf")
+    name = "fc_bake_sdf" if cull else "fc_bake_sdf_unculled"
+    _check(getattr(lib(), name)(_ptr(table.table), table.n_tris, nx, ny, nz, o, float(h), _ptr(out), _stream(stream)),
+           name)
     return out
 
 
@@ -484,6 +592,11 @@ class Graph:
     """An instantiated hipGraph of one step (fused forward and/or backward)."""
 
     def __init__(self, batch: Batch, pose, fused_out=None, k=0.0, grads=None, upstream=None):
+        _check_pose(batch, pose)
+        if fused_out is not None:
+            _check_contacts(batch, fused_out)
+        if grads is not None:
+            _check_grads(batch, grads, upstream)
         h = C.c_void_p()
         os_ = _contacts_struct(fused_out)
         gs = None if grads is None else _grads_struct(grads)
