@@ -16,6 +16,16 @@ namespace {
 
 constexpr int kF32 = FC_F32, kF16 = FC_F16, kBF16 = FC_BF16;
 
+// Orders a wavefront's own LDS writes (stores and atomics) before its later
+// LDS reads of what other lanes wrote: release and acquire fences at
+// wavefront scope around a wave barrier, so neither the compiler nor the
+// memory model lets the reads move ahead of the writes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // rigid transform (quaternion x,y,z,w -> R = I + 2w[v]x + 2[v]x^2, no renormalisation)
 // ---------------------------------------------------------------------------

@@ -731,6 +731,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
           atomicMax(&s_wkeys[bin], make_key(-phi, (unsigned)(it.vstart + j * kBwdBlock + tid)));
         }
       }
+      wave_lds_sync();  // the lanes' LDS atomics before the per-bin reads
       if (lane < F.K) {
         const unsigned long long kk = s_wkeys[lane];
         if (kk) {
@@ -801,8 +802,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
       }
     }
     if constexpr (QUERY) {
-      // The wavefront's LDS atomics precede these reads in its own DS
-      // instruction stream, which the LDS executes in order.
+      wave_lds_sync();  // the lanes' LDS atomics before the per-bin reads
       if (lane < F.K) {
         const unsigned long long kk = s_wkeys[lane];
         if (kk) {

@@ -264,9 +264,7 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
           s_pmem[slot] = members;
           s_pfound[slot] = (int)key_vidx(best);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_lds_sync();
       }
       if (lane == 0) s_np = np;
     }
