@@ -4,18 +4,24 @@ the C ABI.
 
 The descent's accept/reject decisions compare phi values, so an FP32 run and
 an FP64 run may part ways where two values are within rounding of each other;
-both paths are then valid descents.  So the checks are:
-  * for every face, what is unique given the GPU's own result: its phi is the
-    FP64 field at its point (within the FP32 sampling tolerance), the point
-    lies on the face, phi never exceeds the field at the face's centroid,
-    the normal is the FP64 gradient direction there, the bin is the FP32 rule
-    on the GPU's normal, and the reduction is exact on the GPU's candidates;
-  * against the oracle's own descent: the final phi agrees within the FP32
-    tolerance for at least 99 % of the faces."""
+both paths are then valid descents.  So, for every face:
+  * what is unique given the GPU's own result: its phi is the FP64 field at
+    its point (within the FP32 sampling tolerance), the point lies on the
+    face, phi never exceeds the field at the face's centroid, the normal is
+    the FP64 gradient direction there (within its FP32 bound; within the
+    FP32 position error of a cell face, either cell's), the bin is the FP32
+    rule on the GPU's normal, and the reduction is exact on the GPU's
+    candidates;
+  * against the oracle's descent: the final phi agrees within the FP32
+    tolerance, or the GPU's end state is one of the ends the FP64 descent
+    reaches when every decision within the FP32 evaluation error goes
+    either way (tests/_faces_common.py)."""
 import numpy as np
 import pytest
 
-from _gpu_common import assert_same, bins_fp32, to_np, torch_gpu
+from _faces_common import decision_tolerance, descent_leaves, matches_a_leaf
+from _gpu_common import (FACE_BAND, _alt_normals, assert_same, bins_fp32, normal_bound, position_error_voxels, to_np,
+                         torch_gpu)
 from oracle import faces as OF
 from oracle import query as OQ
 from oracle import reduce as ORD
@@ -25,7 +31,6 @@ from paper_2205_03532_amd import workloads as W
 pytestmark = pytest.mark.gpu
 ITERS, STEP0 = fc.PGD_ITERS, fc.PGD_STEP0
 PHI_TOL = 1e-6  # m: FP32 sampling and descent rounding, as for vertex queries
-AGREE = 0.99  # fraction of faces whose final phi matches the FP64 descent
 
 
 def face_offsets(w):
@@ -41,6 +46,38 @@ def run_faces(b, pose, iters=ITERS, cand=True, fused=True):
     fc.fc_sdf_query_faces(b, pose, cand=c, fused_out=o, iters=iters, step0=STEP0)
     torch.cuda.synchronize()
     return (to_np(c) if cand else None), (to_np(o) if fused else None)
+
+
+def check_face_normals(w, g0, gx, gn, grad_at, phi_at, idx, rows):
+    """Every candidate's normal against the FP64 gradient direction at the
+    GPU's own point, within its FP32 bound; a point within the FP32 position
+    error of a cell face may take the neighbouring cell's gradient, so those
+    are compared with the normals across every near face."""
+    if not len(idx):
+        return
+    h = float(g0.h)
+    u = (gx[idx] - np.asarray(g0.origin, np.float64)) / h
+    _, _, _, cells = OQ.sample(OQ.grid_values_f64(g0.values, g0.dtype), g0.origin, g0.h, g0.dims, gx[idx])
+    o = dict(x_b=gx[idx], u=u, h=np.full(len(idx), h), env=np.zeros(len(idx), np.int64), cell=cells,
+             grad=grad_at[idx], phi=phi_at[idx])
+    wz = W.Workload(w.name, [g0], w.meshes[:1], np.zeros(1, np.int32), np.zeros(1, np.int32), w.pose[:, :1],
+                    w.bins, w.margin)
+    du = np.max(position_error_voxels(o), axis=1)
+    tol = normal_bound(wz, o, du)
+    gl = np.linalg.norm(grad_at[idx], axis=1)
+    ref = grad_at[idx] / np.where(gl > 0, gl, 1.0)[:, None]
+    nerr = np.linalg.norm(gn[idx] - ref, axis=1)
+    band = np.maximum(FACE_BAND, 2.0 * du)
+    t = u - np.floor(u)
+    near = np.any((t < band[:, None]) | (t > 1 - band[:, None]), axis=1)
+    bad = (nerr > tol) & ~near
+    assert not bad.any(), f"normal mismatch at face rows {rows[idx[bad]][:10]} err {nerr[bad][:5]} tol {tol[bad][:5]}"
+    nf = np.nonzero(near & (nerr > tol))[0]
+    if len(nf):
+        ok = np.zeros(len(nf), bool)
+        for a, ta in _alt_normals(wz, o, nf, band):
+            ok |= np.linalg.norm(gn[idx[nf]] - a, axis=1) <= ta
+        assert ok.all(), f"near-face normal mismatch at face rows {rows[idx[nf[~ok]]][:10]}"
 
 
 def check_faces(w, c, o, envs, iters=ITERS):
@@ -75,21 +112,23 @@ def check_faces(w, c, o, envs, iters=ITERS):
     assert np.all(resid[on] <= 1e-5 * scale[on] + 1e-9)
     # never above the start
     assert np.all(gp[g_in] <= r["phi0"][g_in] + PHI_TOL)
-    # agreement with the FP64 descent
-    both = g_in & np.isfinite(r["phi"])
-    agree = np.abs(gp[both] - r["phi"][both]) <= PHI_TOL
-    frac = agree.mean() if both.any() else 1.0
-    assert frac >= AGREE, frac
-    assert (g_in != np.isfinite(r["phi"])).mean() <= 1 - AGREE
+    # agreement with the FP64 descent, or a branch of it through decisions
+    # within the FP32 evaluation error
+    o_fin = np.isfinite(r["phi"])
+    agree = (g_in == o_fin) & (~g_in | (np.abs(gp - np.where(o_fin, r["phi"], 0.0)) <= PHI_TOL))
+    scale = np.sqrt(np.sum(e1 * e1, 1) + np.sum(e2 * e2, 1))
+    for i in np.nonzero(~agree)[0]:
+        tau = decision_tolerance(X[i], g0.origin, g0.h, g0.dims)
+        lx, lp = descent_leaves(vals, g0.origin, g0.h, g0.dims, X[i], iters, STEP0, tau)
+        gphi = gp[i] if g_in[i] else np.inf
+        assert matches_a_leaf(gx[i], gphi, lx, lp, PHI_TOL, 1e-5 * scale[i] + 1e-9), \
+            f"face row {rows[i]}: gpu phi {gphi}, oracle {r['phi'][i]}, {len(lp)} branch ends"
     # candidates, normals, bins
     cand = g_in & (gp < np.float32(w.margin))
     b = c["bin"][rows].astype(np.int64)
     assert np.array_equal(b >= 0, cand)
     gn = c["normal"][:, rows].T.astype(np.float64)
-    gnorm = np.linalg.norm(grad_at, axis=1)
-    ref_n = grad_at / np.where(gnorm > 0, gnorm, 1)[:, None]
-    nerr = np.linalg.norm(gn[cand] - ref_n[cand], axis=1)
-    assert np.mean(nerr <= 1e-5) >= AGREE, np.mean(nerr <= 1e-5)
+    check_face_normals(w, g0, gx, gn, grad_at, phi_at, np.nonzero(cand)[0], rows)
     sel = np.nonzero(cand)[0]
     assert np.array_equal(bins_fp32(c["normal"][:, rows[sel]], w.bins), b[sel])
     # exact reduction of the GPU's own candidates; winners' records are the candidates'
@@ -107,7 +146,8 @@ def check_faces(w, c, o, envs, iters=ITERS):
         assert np.array_equal(o["point"][:, s][:, full].view(np.uint32), c["point"][:, q].view(np.uint32)), e
         assert np.array_equal(o["normal"][:, s][:, full].view(np.uint32), c["normal"][:, q].view(np.uint32)), e
         assert o["count"][e] == int(full.sum())
-    return dict(faces=int(len(rows)), inside=int(g_in.sum()), cand=int(cand.sum()), agree=float(frac))
+    return dict(faces=int(len(rows)), inside=int(g_in.sum()), cand=int(cand.sum()),
+                branched=int((~agree).sum()))
 
 
 def test_torus_faces_match_oracle():
