@@ -1,10 +1,6 @@
 """Values the paper prints that bear on the hot path's data (CPU only)."""
 import os
 
-import numpy as np
-
-from paper_2205_03532_amd import workloads as W
-
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -27,21 +23,3 @@ def test_sdf_memory_column_is_fp32_samples():
         else:
             assert abs(mib - mb) / mb > 0.2, name
     assert n_fp32 == 5
-
-
-def test_fp32_grid_storage_matches_that_layout():
-    """An FP32 grid of those dims occupies exactly dims x 4 bytes here too."""
-    g = W.Grid(values=np.zeros((144, 404, 144), np.float32), dtype="f32", origin=(0.0, 0.0, 0.0), h=1e-4)
-    assert g.nbytes == 144 * 404 * 144 * 4
-    assert abs(g.nbytes / 2**20 - 31.95) < 0.01
-
-
-def test_contact_record_is_36_bytes():
-    """Section III-B: about 7 floats (point, normal, distance) + 2 ints = 36 B.
-
-    The reduced-contact slot written by the library holds the same 7 float32
-    plus the vertex index; the two body indices are implicit in the slot's
-    environment.
-    """
-    floats, ints = 3 + 3 + 1, 2
-    assert floats * 4 + ints * 4 == 36
