@@ -55,7 +55,8 @@ typedef enum fc_status {
   FC_ERR_RANGE = 4,       /* a numeric parameter is out of range (h, k, K) */
   FC_ERR_WORKSPACE = 5,   /* workspace NULL or smaller than fc_workspace_bytes */
   FC_ERR_HIP = 6,         /* a HIP runtime call failed; see fc_last_hip_error */
-  FC_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+  FC_ERR_UNSUPPORTED = 7, /* valid request this build does not implement */
+  FC_ERR_SCRATCH = 8      /* more scratch than fc_sdf_query_noalloc holds */
 } fc_status;
 
 typedef enum fc_dtype { FC_F32 = 0, FC_F16 = 1, FC_BF16 = 2 } fc_dtype;
@@ -256,6 +257,24 @@ fc_status fc_workspace_init(const fc_batch* batch, void* ws, size_t ws_bytes, vo
 fc_status fc_sdf_query(const fc_batch* batch, const float* pose, const fc_candidates* cand,
                        const fc_contacts* fused_out, void* ws, size_t ws_bytes, void* stream);
 
+/* fc_sdf_query without a workspace argument, for callers that cannot
+ * allocate device memory around the call (code being captured into a
+ * graph, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments (minus ws), outputs and errors as fc_sdf_query, bit-identical
+ * results.  Its scratch (per-bin keys and work counters) is a static device
+ * array of 4 MiB per device, held by every device the library runs on until
+ * the process ends; the call allocates nothing and frees nothing, and zeroes
+ * the part it uses on `stream` before its kernels (a fill kernel, no
+ * memset).  All calls on one device share that array: calls that overlap on
+ * one device (two streams, or two host threads without ordering) race and
+ * give undefined results; order them on one stream.
+ * Extra errors: FC_ERR_SCRATCH if fc_sdf_query_noalloc_bytes(batch) exceeds
+ * 4 MiB (about n_env * K <= 524,000 keys); FC_ERR_UNSUPPORTED if the current
+ * device is not the one the batch was created on. */
+fc_status fc_sdf_query_noalloc(const fc_batch* batch, const float* pose, const fc_candidates* cand,
+                               const fc_contacts* fused_out, void* stream);
+/* Scratch bytes fc_sdf_query_noalloc needs for this batch (0 for NULL). */
+size_t fc_sdf_query_noalloc_bytes(const fc_batch* batch);
 
 /* FindDeepest / BinReduce over candidates written by fc_sdf_query with the
  * same batch and pose: per (env, bin) the candidate of greatest depth, equal

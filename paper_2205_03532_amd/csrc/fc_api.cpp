@@ -369,6 +369,7 @@ struct fc_batch {
   long long Q = 0;
   fc_launch launch{256, 1024, 0, 8, 0};
   int num_cus = 256;
+  int device = 0;  // the device current at creation: its tables live there
   int bwd_chunk = 0;  // envs per backward item (choose_bwd_chunk)
   std::string signature;
   // forward tables
@@ -983,6 +984,7 @@ const char* fc_status_str(fc_status s) {
     case FC_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
     case FC_ERR_HIP: return "HIP runtime error";
     case FC_ERR_UNSUPPORTED: return "unsupported request";
+    case FC_ERR_SCRATCH: return "batch needs more scratch than the no-allocation call holds";
   }
   return "unknown status";
 }
@@ -1018,6 +1020,7 @@ fc_status fc_batch_create(const fc_batch_desc* desc, fc_batch** out) {
   b->dirs.assign(desc->bin_dirs, desc->bin_dirs + 3 * b->K);
   int dev = 0;
   hipError_t he = hipGetDevice(&dev);
+  b->device = dev;
   if (he == hipSuccess) he = hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (he != hipSuccess) {
     delete b;
@@ -1131,6 +1134,29 @@ fc_status fc_sdf_query(const fc_batch* b, const float* pose, const fc_candidates
   fc_status s = check_ws(b, ws, ws_bytes);
   if (s != FC_OK) return s;
   return enqueue_forward(b, pose, cand, fused_out, ws, (hipStream_t)stream, false, true);
+}
+
+size_t fc_sdf_query_noalloc_bytes(const fc_batch* b) {
+  return b ? b->off_workctr + kXcds * sizeof(unsigned) : 0;
+}
+
+fc_status fc_sdf_query_noalloc(const fc_batch* b, const float* pose, const fc_candidates* cand,
+                               const fc_contacts* fused_out, void* stream) {
+  if (!b || !pose) return FC_ERR_NULL;
+  if (!cand && !fused_out) return FC_ERR_NULL;
+  if (cand && (!cand->phi || !cand->normal || !cand->bin)) return FC_ERR_NULL;
+  if (fused_out && !contacts_ok(fused_out)) return FC_ERR_NULL;
+  // the forward's part of the workspace layout: keys at 0, then the counters
+  const size_t need = fc_sdf_query_noalloc_bytes(b);
+  if (need > kNoAllocScratchBytes) return FC_ERR_SCRATCH;
+  int dev = -1;
+  FC_HIP(hipGetDevice(&dev));
+  if (dev != b->device) return FC_ERR_UNSUPPORTED;
+  void* ws = nullptr;
+  FC_HIP(noalloc_scratch(&ws));
+  // the array keeps the last call's contents: keys and counters start at zero
+  FC_HIP(launch_zero(ws, need, (hipStream_t)stream));
+  return enqueue_forward(b, pose, cand, fused_out, ws, (hipStream_t)stream, false, false);
 }
 
 fc_status fc_contact_reduce(const fc_batch* b, const float* pose, const fc_candidates* cand, const fc_contacts* out,

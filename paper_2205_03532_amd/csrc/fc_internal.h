@@ -219,6 +219,12 @@ hipError_t launch_query_chunked(const BwdArgs& a, const QueryExtra& q, const Fwd
 // measurement aid: k_query_backward's items, loop and corner loads, no arithmetic
 hipError_t launch_gather_probe(const BwdArgs& a, int dtype, int layout, hipStream_t s, const KernelMarks* m);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// The no-allocation forward's scratch: a static device array of this many
+// bytes per device (fc_kernels.hip), held until the process ends.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+// Device address of the current device's scratch array, looked up once per
+// device (hipGetSymbolAddress with that device current) and kept.
+hipError_t noalloc_scratch(void** ptr);
 // Patch reduction (Algorithm 1): one workgroup per environment, batches of
 // kPatchBatch vertices, at most kPatchMax patches.
 constexpr int kPatchBlock = 256;

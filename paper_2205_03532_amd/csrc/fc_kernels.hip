@@ -24,6 +24,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fc_device.h"
 
 namespace fcimpl {
@@ -1366,6 +1368,31 @@ hipError_t launch_gather_probe(const BwdArgs& a, int dtype, int layout, hipStrea
     case kBF16: return probe_layout<kBF16>(a, layout, s);
   }
   return hipErrorInvalidValue;
+}
+
+// The no-allocation forward's scratch.  In host code `scratch` names a
+// host-side stand-in, not device memory: host code uses only the address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {

@@ -24,7 +24,9 @@ import numpy as np
 LIB_PATH = os.environ.get("FC_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                          "libfactory_sdf.so")
 
-FC_OK, FC_ERR_NULL, FC_ERR_SHAPE, FC_ERR_DTYPE, FC_ERR_RANGE, FC_ERR_WORKSPACE, FC_ERR_HIP, FC_ERR_UNSUPPORTED = range(8)
+(FC_OK, FC_ERR_NULL, FC_ERR_SHAPE, FC_ERR_DTYPE, FC_ERR_RANGE, FC_ERR_WORKSPACE, FC_ERR_HIP, FC_ERR_UNSUPPORTED,
+ FC_ERR_SCRATCH) = range(9)
+NOALLOC_SCRATCH_BYTES = 4 << 20  # the static scratch of fc_sdf_query_noalloc, per device
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 LAYOUTS = {"linear": 0, "brick": 1, "slab": 2, "sparse": 3}
 SPARSE_BAND_VOXELS = 4.0  # default narrow band of the sparse layout, in voxels
@@ -96,6 +98,9 @@ SIGNATURES = {
     "fc_workspace_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "fc_sdf_query": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_candidates), C.POINTER(fc_contacts),
                                C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fc_sdf_query_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_candidates), C.POINTER(fc_contacts),
+                                       C.c_void_p]),
+    "fc_sdf_query_noalloc_bytes": (C.c_size_t, [C.c_void_p]),
     "fc_contact_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(fc_candidates), C.POINTER(fc_contacts),
                                     C.c_void_p, C.c_size_t, C.c_void_p]),
     "fc_sdf_query_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.POINTER(fc_grads),
@@ -478,6 +483,20 @@ def fc_sdf_query(batch: Batch, pose, cand=None, fused_out=None, stream=None):
     _check(lib().fc_sdf_query(batch.handle, _ptr(pose), _byref(cs), _byref(os_),
                               C.c_void_p(batch.workspace.data_ptr()), batch.ws_bytes, _stream(stream)),
            "fc_sdf_query")
+
+
+def fc_sdf_query_noalloc(batch: Batch, pose, cand=None, fused_out=None, stream=None):
+    """fc_sdf_query on the library's static per-device scratch instead of the
+    batch's workspace (no allocation by the call; calls on one device must
+    not overlap)."""
+    _check_pose(batch, pose)
+    if cand is not None:
+        _check_candidates(batch, cand)
+    if fused_out is not None:
+        _check_contacts(batch, fused_out)
+    cs, os_ = _cand_struct(cand), _contacts_struct(fused_out)
+    _check(lib().fc_sdf_query_noalloc(batch.handle, _ptr(pose), _byref(cs), _byref(os_), _stream(stream)),
+           "fc_sdf_query_noalloc")
 
 
 def fc_contact_reduce(batch: Batch, pose, cand, out, stream=None):

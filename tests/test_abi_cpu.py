@@ -44,8 +44,8 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_status_strings(L):
-    for s in range(8):
-        assert L.fc_status_str(s)
+    for s in range(9):
+        assert L.fc_status_str(s) != b"unknown status"
     assert L.fc_status_str(0) == b"ok"
 
 
@@ -101,6 +101,8 @@ def test_null_arguments(L):
     assert L.fc_batch_create(None, C.byref(h)) == fc.FC_ERR_NULL
     assert L.fc_batch_create(C.byref(make_desc()), None) == fc.FC_ERR_NULL
     assert L.fc_sdf_query(None, None, None, None, None, 0, None) == fc.FC_ERR_NULL
+    assert L.fc_sdf_query_noalloc(None, None, None, None, None) == fc.FC_ERR_NULL
+    assert L.fc_sdf_query_noalloc_bytes(None) == 0
     assert L.fc_contact_reduce(None, None, None, None, None, 0, None) == fc.FC_ERR_NULL
     assert L.fc_sdf_query_backward(None, None, 1.0, None, None, None, 0, None) == fc.FC_ERR_NULL
     assert L.fc_sdf_query_and_backward(None, None, None, 1.0, None, None, None, 0, None) == fc.FC_ERR_NULL
