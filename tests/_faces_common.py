@@ -29,6 +29,17 @@ def decision_tolerance(X, origin, h, dims):
     return 3.0 * 8.0 * ULP32 * L * 1.5
 
 
+def point_tolerance(X, origin, h, dims):
+    """Largest distance between the end point of an FP32 run and that of the
+    FP64 descent on the same branch: the FP32 point carries the rounding of
+    its corners (R v + t) and of the barycentric combination, a few ulp of
+    the largest coordinate L each; 8 ulp of L, taken with a factor 3 as in
+    decision_tolerance."""
+    far = np.abs(np.asarray(origin, np.float64)) + h * (np.asarray(dims, np.float64) - 1.0)
+    L = max(float(np.max(np.abs(X))), float(np.max(far)))
+    return 3.0 * 8.0 * ULP32 * L
+
+
 def _sample(vals, origin, h, dims, x, band):
     """phi (+inf outside), grad, and a flag for points within ``band`` voxels
     of the grid's boundary, where an FP32 run may call the point inside (with
@@ -43,10 +54,44 @@ def _sample(vals, origin, h, dims, x, band):
     return phi, g, near, pc, gc
 
 
-def descent_leaves(vals, origin, h, dims, X, iters, step0, tau, band=1e-4):
+def alt_grads(vals, origin, h, dims, x, band):
+    """The other gradients an FP32 run may take at the inside point x: within
+    ``band`` voxels of an interior cell face it may place x in the cell on
+    the other side, where the interpolant has the same value (it is
+    continuous) but another gradient.  One per combination of such faces."""
+    n = np.asarray(dims, np.int64)
+    u = (np.asarray(x, np.float64) - np.asarray(origin, np.float64)) / h
+    cell = np.clip(np.floor(u), 0, n - 2).astype(np.int64)
+    t = u - cell
+    opts = []
+    for ax in range(3):
+        o = [0]
+        if t[ax] < band and cell[ax] > 0:
+            o.append(-1)
+        if t[ax] > 1.0 - band and cell[ax] < n[ax] - 2:
+            o.append(1)
+        opts.append(o)
+    out = []
+    for sx in opts[0]:
+        for sy in opts[1]:
+            for sz in opts[2]:
+                if sx == 0 and sy == 0 and sz == 0:
+                    continue
+                c2 = cell + np.array([sx, sy, sz])
+                _, g2 = OQ.trilinear_value_grad(vals, c2[None], (u - c2)[None], h)
+                out.append(g2[0])
+    return out
+
+
+def descent_leaves(vals, origin, h, dims, X, iters, step0, tau, band=1e-4, face_band=None):
     """End states (x (m, 3), phi (m,)) of the FP64 descent of one face
     (corners X (3, 3) in B's frame) over every branch of its ambiguous
-    decisions; phi is +inf for an end point outside the grid."""
+    decisions; phi is +inf for an end point outside the grid.  An accepted
+    point within ``face_band`` voxels of a cell face (default: the position
+    error bound of point_tolerance) also branches on the gradient of each
+    cell it may be placed in, which steers the next trial."""
+    if face_band is None:
+        face_band = max(band, point_tolerance(X, origin, h, dims) / h)
     X = np.asarray(X, np.float64)
     xa, e1, e2 = X[0], X[1] - X[0], X[2] - X[0]
     S = (e1 @ e1 + e2 @ e2 + (e2 - e1) @ (e2 - e1)) / 3.0
@@ -67,6 +112,18 @@ def descent_leaves(vals, origin, h, dims, X, iters, step0, tau, band=1e-4):
         phi = np.concatenate([phi, alt_phi])
         g = np.concatenate([g, alt_g])
         alpha = np.repeat(alpha, 2)
+
+    def with_cell_gradients(rows, b, x, phi, g, alpha):
+        """Adds, for each listed state, copies with the other cells' gradients."""
+        extra = [(b[i], x[i], phi[i], ga, alpha[i]) for i in rows if np.isfinite(phi[i])
+                 for ga in alt_grads(vals, origin, h, dims, x[i], face_band)]
+        if not extra:
+            return b, x, phi, g, alpha
+        eb, ex, ep, eg, ea = (np.asarray(v) for v in zip(*extra))
+        return (np.concatenate([b, eb]), np.concatenate([x, ex]), np.concatenate([phi, ep]),
+                np.concatenate([g, eg]), np.concatenate([alpha, ea]))
+
+    b, x, phi, g, alpha = with_cell_gradients(range(len(b)), b, x, phi, g, alpha)
     for _ in range(iters):
         d = np.stack([np.zeros(len(b)), g @ e1, g @ e2], axis=1)
         bt = OF.trial_point(b, alpha, d)
@@ -106,6 +163,7 @@ def descent_leaves(vals, origin, h, dims, X, iters, step0, tau, band=1e-4):
         phi = np.where(acc, np.asarray(rows_pt), phi[idx])
         g = np.where(acc[:, None], np.asarray(rows_gt), g[idx])
         alpha = np.where(acc, 2.0 * alpha[idx], 0.5 * alpha[idx])
+        b, x, phi, g, alpha = with_cell_gradients(np.nonzero(acc)[0], b, x, phi, g, alpha)
         if len(b) > 4096:
             raise RuntimeError("too many ambiguous decisions on one face")
     return x, phi

@@ -19,7 +19,7 @@ both paths are then valid descents.  So, for every face:
 import numpy as np
 import pytest
 
-from _faces_common import decision_tolerance, descent_leaves, matches_a_leaf
+from _faces_common import decision_tolerance, descent_leaves, matches_a_leaf, point_tolerance
 from _gpu_common import (FACE_BAND, _alt_normals, assert_same, bins_fp32, normal_bound, position_error_voxels, to_np,
                          torch_gpu)
 from oracle import faces as OF
@@ -121,7 +121,8 @@ def check_faces(w, c, o, envs, iters=ITERS):
         tau = decision_tolerance(X[i], g0.origin, g0.h, g0.dims)
         lx, lp = descent_leaves(vals, g0.origin, g0.h, g0.dims, X[i], iters, STEP0, tau)
         gphi = gp[i] if g_in[i] else np.inf
-        assert matches_a_leaf(gx[i], gphi, lx, lp, PHI_TOL, 1e-5 * scale[i] + 1e-9), \
+        x_tol = point_tolerance(X[i], g0.origin, g0.h, g0.dims)
+        assert matches_a_leaf(gx[i], gphi, lx, lp, PHI_TOL, x_tol), \
             f"face row {rows[i]}: gpu phi {gphi}, oracle {r['phi'][i]}, {len(lp)} branch ends"
     # candidates, normals, bins
     cand = g_in & (gp < np.float32(w.margin))
