@@ -347,6 +347,124 @@ def measure_patches(batch, pose, n, warmup):
             "batch_vertices": 1024, "patches_per_env_mean": float(cnt.mean()), "patches_per_env_max": int(cnt.max())}
 
 
+def step_roofline(b, pose, n, warmup, bpq):
+    """Mean duration of the one-pass kernel (library events on the launch
+    stream) and of the gather probe on batch b; the algorithmic rate."""
+    import torch
+
+    from paper_2205_03532_amd import fc
+
+    o, g = b.new_contacts(), b.new_grads(per_env=False)
+    sink = torch.zeros(1, device=b.device)
+    for _ in range(warmup):
+        fc.fc_sdf_query_and_backward(b, pose, o, K_PENALTY, g)
+        fc.fc_gather_probe(b, pose, sink)
+    b.set_timing(n)
+    for _ in range(n):
+        fc.fc_sdf_query_and_backward(b, pose, o, K_PENALTY, g)
+    k_one, kid = b.read_timing()
+    assert np.all(kid == fc.FC_KERNEL_QUERY_BACKWARD)
+    b.set_timing(n)
+    for _ in range(n):
+        fc.fc_gather_probe(b, pose, sink)
+    k_probe, kid = b.read_timing()
+    b.set_timing(0)
+    assert np.all(kid == fc.FC_KERNEL_GATHER_PROBE)
+    torch.cuda.synchronize()
+    kms, pms = float(k_one.mean()), float(k_probe.mean())
+    ach = bpq * b.Q / (kms * 1e-3) / 1e9
+    return {"kernel": "k_query_backward", "kernel_ms": kms, "alg_bytes_per_query": bpq, "achieved": ach,
+            "unit": "GB/s", "hbm_peak": HBM_PEAK_GBS, "frac_of_hbm_peak": ach / HBM_PEAK_GBS,
+            "gather_probe_ms": pms, "frac_of_achievable_gather": pms / kms}
+
+
+def contact_errors(w32, cand, envs):
+    """Depth and normal error of a batch's candidates against the FP64 oracle
+    on the FP32 grids of w32, over every contact of the listed envs (queries
+    the oracle makes candidates and both sides place inside the grid)."""
+    from oracle import query as OQ
+
+    o = OQ.query_workload(w32, envs)
+    off = w32.env_query_offsets()
+    rows = np.concatenate([np.arange(off[e], off[e + 1]) for e in envs])
+    phi = cand["phi"].cpu().numpy()[rows].astype(np.float64)
+    nrm = cand["normal"].cpu().numpy()[:, rows].T.astype(np.float64)
+    c = o["cand"] & np.isfinite(phi)
+    derr = np.abs(phi[c] - o["phi"][c])
+    nerr = np.linalg.norm(nrm[c] - o["normal"][c], axis=1)
+    near = np.abs(o["phi"][c]) < 1e-3
+
+    def q(a, p):
+        return float(np.percentile(a, p)) if a.size else 0.0
+    return {"contacts": int(c.sum()), "envs": len(envs),
+            "max_depth_err_m": float(derr.max()) if derr.size else 0.0,
+            "max_depth_err_m_within_1mm": float(derr[near].max()) if near.any() else 0.0,
+            "p99_depth_err_m": q(derr, 99),
+            "max_normal_err": float(nerr.max()) if nerr.size else 0.0,
+            "p99_normal_err": q(nerr, 99), "p50_normal_err": q(nerr, 50),
+            "normal_err_unit": "chord |n - n_fp64| (radians for small angles)"}
+
+
+def sample_envs_per_type(w, per_type, seed=0):
+    rng = np.random.default_rng(seed)
+    envs = []
+    for t in range(len(w.meshes)):
+        ids = np.nonzero(w.env_mesh == t)[0]
+        envs += list(rng.choice(ids, min(per_type, len(ids)), replace=False))
+    return sorted(int(e) for e in envs)
+
+
+def measure_torus(device, n, warmup):
+    """The L2-resident case: analytic torus (R = 2 cm, r = 0.5 cm) on a 64^3
+    FP32 grid (1 mm), 2,562-vertex icosphere, 256 random poses, K = 16.  The
+    1 MiB grid sits in every XCD's 4 MB L2, so the ceiling is the gather
+    probe (L2 and texture units), not HBM.  Depth error over all 256 envs."""
+    import torch
+
+    from paper_2205_03532_amd import fc
+    from paper_2205_03532_amd import workloads as W
+
+    w = W.torus_workload()
+    b = make_batch(w, device)
+    pose = fc.pose_tensor(w.pose, device)
+    o, g = b.new_contacts(), b.new_grads(per_env=False)
+    ms_one = time_calls(lambda: fc.fc_sdf_query_and_backward(b, pose, o, K_PENALTY, g), n, warmup)
+    ms_fwd = time_calls(lambda: fc.fc_sdf_query(b, pose, fused_out=o), n, warmup)
+    rl = step_roofline(b, pose, n, warmup, alg_bytes_per_query("f32"))
+    rl["bound"] = "l2 gather (grid resident in each XCD's L2)"
+    cand = b.new_candidates()
+    fc.fc_sdf_query(b, pose, cand=cand)
+    torch.cuda.synchronize()
+    err = contact_errors(w, cand, list(range(w.n_env)))
+    return {"workload": "torus R = 2 cm, r = 0.5 cm, 64^3 FP32 grid (h = 1 mm); icosphere r = 1 cm, "
+                        f"{w.meshes[0].n} vertices; {w.n_env} poses; K = {w.K}",
+            "queries_per_step": b.Q, "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3),
+            "fwd_queries_per_s": b.Q / (ms_fwd * 1e-3), "call_ms": {"query_and_backward": ms_one, "query": ms_fwd},
+            "roofline": rl, "errors_vs_fp64_oracle_all_envs": err, "launch": b.get_launch()}
+
+
+def measure_nutbolt_1024(device, n, warmup):
+    """Forward plus backward on 1,024 nut-bolt envs (the differentiation
+    configuration; its gradients are checked against FP64 finite differences
+    on 64 envs by the parity tests)."""
+    from paper_2205_03532_amd import fc
+    from paper_2205_03532_amd import workloads as W
+
+    w = W.nut_bolt_workload(n_env=1024)
+    b = make_batch(w, device)
+    pose = fc.pose_tensor(w.pose, device)
+    o, g = b.new_contacts(), b.new_grads(per_env=False)
+    ms_one = time_calls(lambda: fc.fc_sdf_query_and_backward(b, pose, o, K_PENALTY, g), n, warmup)
+    ms_sep = time_calls(lambda: (fc.fc_sdf_query(b, pose, fused_out=o),
+                                 fc.fc_sdf_query_backward(b, pose, K_PENALTY, g)), n, warmup)
+    rl = step_roofline(b, pose, n, warmup, alg_bytes_per_query("f32"))
+    return {"workload": f"nut-on-bolt, {w.n_env} envs x {w.meshes[0].n} vertices, 256x256x512 FP32 bolt SDF, "
+                        "penalty 0.5 k depth^2 (k = 1e4), gradients for pose twists and shared vertices",
+            "queries_per_step": b.Q, "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3),
+            "separate_fwd_then_bwd_queries_per_s": b.Q / (ms_sep * 1e-3), "call_ms": ms_one,
+            "roofline": rl, "launch": b.get_launch()}
+
+
 def measure_forms(w32, device, n, warmup):
     """The other forms of the path beside the FP32 nut-bolt step: the same
     batch with FP16 and BF16 grid storage, with narrow-band sparse storage,
@@ -374,6 +492,8 @@ def measure_forms(w32, device, n, warmup):
             "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3), "fwd_queries_per_s": b.Q / (ms_fwd * 1e-3),
             "alg_bytes_per_query": alg_bytes_per_query(dt),
             "max_depth_err_m_vs_fp32_grid_oracle": depth_check(w32, cand["phi"].cpu().numpy()),
+            "errors_vs_fp32_grid_fp64_oracle": contact_errors(w32, cand, [0, 1, 2, 3]),
+            "roofline": step_roofline(b, pose, n, warmup, alg_bytes_per_query(dt)),
             "launch": b.get_launch()}
         del b, o, g, cand
     # narrow-band sparse storage of the same FP32 grid (4-voxel band): every nut
@@ -408,7 +528,32 @@ def measure_forms(w32, device, n, warmup):
     ms_fwd = time_calls(g_fwd.launch, n, warmup)
     out["mixed_4096_envs_5_types_graph"] = {
         "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3), "fwd_queries_per_s": b.Q / (ms_fwd * 1e-3),
-        "queries_per_step": b.Q, "launch": b.get_launch()}
+        "queries_per_step": b.Q, "launch": b.get_launch(),
+        "roofline": step_roofline(b, pose, n, warmup, alg_bytes_per_query("f32"))}
+    del b, o, g, g_one, g_fwd
+    # the same uneven batch with every grid in FP16, then BF16: depth and normal
+    # error against the FP64 oracle on the FP32 grids over all contacts of two
+    # sampled envs per part type
+    envs = sample_envs_per_type(wm, 2, seed=3)
+    for dt in ("f16", "bf16"):
+        wh = W.half_storage(wm, dt)
+        b = make_batch(wh, device)
+        pose = fc.pose_tensor(wh.pose, device)
+        o, g = b.new_contacts(), b.new_grads(per_env=False)
+        g_one = fc.fc_graph_create(b, pose, fused_out=o, k=K_PENALTY, grads=g)
+        g_fwd = fc.fc_graph_create(b, pose, fused_out=o)
+        ms_one = time_calls(g_one.launch, n, warmup)
+        ms_fwd = time_calls(g_fwd.launch, n, warmup)
+        cand = b.new_candidates()
+        fc.fc_sdf_query(b, pose, cand=cand)
+        torch.cuda.synchronize()
+        out[f"mixed_4096_envs_5_types_{dt}_graph"] = {
+            "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3), "fwd_queries_per_s": b.Q / (ms_fwd * 1e-3),
+            "queries_per_step": b.Q, "alg_bytes_per_query": alg_bytes_per_query(dt),
+            "errors_vs_fp32_grid_fp64_oracle": contact_errors(wm, cand, envs),
+            "roofline": step_roofline(b, pose, n, warmup, alg_bytes_per_query(dt)),
+            "launch": b.get_launch()}
+        del b, o, g, g_one, g_fwd, cand
     return out
 
 
@@ -612,6 +757,10 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "limiter": "gather: texture address/data units and L1 line traffic (most corner lines hit in "
+                       "L2/MALL, so DRAM moves far fewer bytes than the algorithmic count)",
+            "dram_GBps": (traffic / (kms * 1e-3) / 1e9) if traffic else None,
+            "dram_frac": (traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
             "alg_bytes_per_query": bpq,
             "achievable_gather": {
                 "probe": "fc_gather_probe: the same kernel loop, work items and corner loads, no arithmetic",
@@ -625,6 +774,8 @@ def main():
         res["forms"] = {"nutbolt_faces_pgd": measure_faces(batch, pose, n, args.warmup),
                         "nutbolt_patch_reduction": measure_patches(batch, pose, n, args.warmup)}
         res["forms"].update(measure_forms(w, dev, n, args.warmup))
+        res["forms"]["torus64_icosphere_256_poses"] = measure_torus(dev, n, args.warmup)
+        res["forms"]["nutbolt_1024_envs_fwd_bwd"] = measure_nutbolt_1024(dev, n, args.warmup)
         res["forms"]["m4_bolt_mesh_bake"] = measure_bake(n, args.warmup, 0 if args.no_cpu_baseline else 100)
     res["host"] = host_info()
     if not args.no_cpu_baseline:
