@@ -227,9 +227,9 @@ constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
 hipError_t noalloc_scratch(void** ptr);
 // Patch reduction (Algorithm 1): one workgroup per environment, batches of
 // kPatchBatch vertices, at most kPatchMax patches.
-constexpr int kPatchBlock = 256;
-constexpr int kPatchVpt = 4;
-constexpr int kPatchBatch = kPatchBlock * kPatchVpt;  // 1024, the paper's batch
+constexpr int kPatchThreads = 256;                      // threads per workgroup
+constexpr int kPatchVpt = 4;                            // vertices per thread and batch
+constexpr int kPatchBatch = kPatchThreads * kPatchVpt;  // 1024, the paper's batch
 constexpr int kPatchMax = 256;
 struct PatchArgs {
   int n_max;       // N, 1 <= N <= kPatchMax

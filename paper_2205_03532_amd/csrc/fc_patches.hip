@@ -21,40 +21,36 @@ __device__ __forceinline__ float dot3_nofma(float ax, float ay, float az, float 
   return (ax * bx + ay * by) + az * bz;
 }
 
-// Wave-wide reductions on the data-parallel primitives instead of LDS
-// permutes: DPP quad xor 1 and xor 2, the 8-lane and 16-lane mirrors (with
-// every lane of a group holding the group's result, a mirror pairs the two
-// halves), a ds_swizzle xor 16, then lanes 0 and 32 read as scalars.  The
-// result is the same in every lane.
+// Wave-wide reductions on the data-parallel primitives: DPP quad xor 1 and
+// xor 2, then the 8-lane and 16-lane mirrors (with every lane of a group
+// holding the group's result, a mirror pairs the two halves), which leaves
+// each 16-lane row's result in all its lanes; the four rows are then read as
+// scalars.  A 64-bit maximum takes the high words' maximum first, then the
+// low words of the lanes that hold it.  The result is the same in every lane.
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp_u32(unsigned v) {
-  return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
-}
-__device__ __forceinline__ unsigned swz16_u32(unsigned v) {
-  return (unsigned)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);  // bit mode: lane i <- lane i ^ 16
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
 }
 __device__ __forceinline__ unsigned long long join64(unsigned lo, unsigned hi) {
   return ((unsigned long long)hi << 32) | lo;
 }
-__device__ __forceinline__ unsigned long long max64_with(unsigned long long v, unsigned lo, unsigned hi) {
-  const unsigned long long w = join64(lo, hi);
-  return w > v ? w : v;
+__device__ __forceinline__ unsigned umax(unsigned a, unsigned b) { return a > b ? a : b; }
+__device__ __forceinline__ unsigned row_max_u32(unsigned v) {
+  v = umax(v, dpp_u32<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = umax(v, dpp_u32<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = umax(v, dpp_u32<0x141>(v));  // lane i <- lane 7-i within each 8 lanes
+  return umax(v, dpp_u32<0x140>(v));  // lane i <- lane 15-i within each row
 }
-template <int CTRL>
-__device__ __forceinline__ unsigned long long max64_dpp(unsigned long long v) {
-  return max64_with(v, dpp_u32<CTRL>((unsigned)v), dpp_u32<CTRL>((unsigned)(v >> 32)));
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = row_max_u32(v);
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return umax(umax(a, b), umax(c, d));
 }
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  v = max64_dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v = max64_dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v = max64_dpp<0x141>(v);  // lane i <- lane 7-i within each 8 lanes
-  v = max64_dpp<0x140>(v);  // lane i <- lane 15-i within each row
-  v = max64_with(v, swz16_u32((unsigned)v), swz16_u32((unsigned)(v >> 32)));
-  const unsigned long long a = join64((unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 0),
-                                      (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 0));
-  const unsigned long long b = join64((unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 32),
-                                      (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 32));
-  return a > b ? a : b;
+  const unsigned hi = wave_max_u32((unsigned)(v >> 32));
+  const unsigned lo = wave_max_u32((unsigned)(v >> 32) == hi ? (unsigned)v : 0u);
+  return join64(lo, hi);
 }
 
 __device__ __forceinline__ int wave_sum_i32(int v) {
@@ -62,8 +58,8 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
   v += (int)dpp_u32<0x4E>((unsigned)v);
   v += (int)dpp_u32<0x141>((unsigned)v);
   v += (int)dpp_u32<0x140>((unsigned)v);
-  v += (int)swz16_u32((unsigned)v);
-  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
 // (d, p) with the largest d, the lowest p on ties
@@ -79,48 +75,66 @@ __device__ __forceinline__ void wave_argmax(float& d, int& p) {
   }
 }
 
-// One workgroup per environment.  For each batch of 1024 vertices: Generate
-// the candidates (the vertex query's values, bit for bit) and compact them in
-// LDS; Assign each to the most similar patch that existed when the batch
-// began (all waves; member counts and deepest keys are order-independent LDS
-// atomics); then one wave repeats FindDeepest / BinReduce / AddPatch until no
-// candidate remains.  Patches live in LDS.
+// One workgroup per environment.  Per batch of kPatchBatch vertices:
+//   Generate  every wave evaluates kPatchVpt vertex queries per thread (the
+//             vertex query's values, bit for bit) and compacts the batch's
+//             candidates into LDS;
+//   Assign    each candidate joins the most similar patch of the list as it
+//             stands after every earlier batch (member counts and deepest
+//             keys by order-independent LDS atomics); the unassigned ones
+//             are packed to the front of the buffer (rank by ballot within
+//             a wave, by the waves' counts across them);
+//   loop      the unassigned entries are dealt to the waves' registers (row
+//             r of 64 to wave r mod 4); per patch each wave finds its
+//             deepest entry, one barrier exchanges the four, every wave
+//             takes the deepest of them (FindDeepest), removes its entries
+//             similar to it (BinReduce) while finding its next deepest, and
+//             the patch is added with its member count summed by LDS
+//             atomics (AddPatch).  The per-wave records alternate between
+//             two LDS slots, so one barrier per patch suffices.
 template <int DT, int LAYOUT>
-__global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P) {
+__global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs P) {
+  constexpr int kWaves = kPatchThreads / 64;
+  constexpr int kRows = kPatchBatch / 64;
+  constexpr int kSlots = kRows / kWaves;  // register rows per wave
+  static_assert(kRows % kWaves == 0, "rows deal evenly to the waves");
+  constexpr int kAsg = kPatchBatch / kPatchThreads;  // Assign entries per thread
+  static_assert(kPatchBatch % kPatchThreads == 0, "Assign covers the buffer");
   __shared__ float s_pn[kPatchMax][3];
   __shared__ unsigned long long s_pkey[kPatchMax];
   __shared__ int s_pmem[kPatchMax];
   __shared__ int s_pfound[kPatchMax];
-  __shared__ int s_np;
   __shared__ unsigned long long s_ck[kPatchBatch];  // the batch's candidates, compacted
   __shared__ float s_cn[kPatchBatch][3];
   __shared__ int s_nc;
+  __shared__ int s_wcnt[kAsg][kWaves];  // unassigned entries per (Assign slot, wave)
+  __shared__ uint4 s_red[2][kWaves];    // each wave's deepest entry: key (x, y), normal x, y (z: s_redz)
+  __shared__ float s_redz[2][kWaves];
+  __shared__ int s_members[2];          // a replaced patch's member count
 
   const int e = blockIdx.x;
   const int gm = A.envs[e].gm;
   const GridDev& g = A.grids[gm & 0xff];
   const MeshDev& m = A.meshes[gm >> 8];
   const Rigid R = load_pose(A.pose, A.n_env, e);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const float cs = P.cos_sim;
-  if (tid == 0) s_np = 0;
-  __syncthreads();
+  for (int p = tid; p < kPatchMax; p += kPatchThreads) s_pmem[p] = 0;  // new patches' counts are summed in
+  if (tid < 2) s_members[tid] = 0;
+  int np = 0;   // patches (the same in every thread)
+  int par = 0;  // LDS record slot of the current patch step
 
   for (int b0 = 0; b0 < m.n; b0 += kPatchBatch) {
     if (tid == 0) s_nc = 0;
     __syncthreads();
-    // Generate, then compact the candidates into LDS: every later step is
-    // independent of their order, and each thread then holds ceil(nc / 256)
-    // of them instead of 4 vertices mostly without a candidate
-    unsigned long long key[kPatchVpt];
-    float nx[kPatchVpt], ny[kPatchVpt], nz[kPatchVpt];
-    bool live[kPatchVpt];
+    // Generate
     {
       float px[kPatchVpt], py[kPatchVpt], pz[kPatchVpt];
       bool ok[kPatchVpt];
 #pragma unroll
       for (int j = 0; j < kPatchVpt; ++j) {
-        const int v = b0 + j * kPatchBlock + tid;
+        const int v = b0 + j * kPatchThreads + tid;
         ok[j] = v < m.n;
         float x = 0.f, y = 0.f, z = 0.f;
         if (ok[j]) {
@@ -144,7 +158,7 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
           float ux, uy, uz;
           normalize(gx, gy, gz, ux, uy, uz);
           const int pos = atomicAdd(&s_nc, 1);
-          s_ck[pos] = make_key(-phi, (unsigned)(b0 + j * kPatchBlock + tid));
+          s_ck[pos] = make_key(-phi, (unsigned)(b0 + j * kPatchThreads + tid));
           s_cn[pos][0] = ux;
           s_cn[pos][1] = uy;
           s_cn[pos][2] = uz;
@@ -152,129 +166,182 @@ __global__ __launch_bounds__(kPatchBlock) void k_patches(FwdArgs A, PatchArgs P)
       }
     }
     __syncthreads();
+    const int nc = s_nc;
+    // Assign, against the patch list as it stands.  The first patch of
+    // largest dot over all patches is the patch of largest dot among the
+    // similar ones (lowest index on ties) whenever it is similar itself, and
+    // no patch is similar otherwise.
+    unsigned long long ak[kAsg];
+    float ax[kAsg], ay[kAsg], az[kAsg];
+    bool un[kAsg];  // unassigned: goes on to the loop
+    const int np0 = __builtin_amdgcn_readfirstlane(np);
+#pragma unroll
+    for (int j = 0; j < kAsg; ++j) {
+      const int i = j * kPatchThreads + tid;
+      ak[j] = 0ull;
+      ax[j] = ay[j] = az[j] = 0.f;
+      un[j] = false;
+      if (i < nc) {
+        ak[j] = s_ck[i];
+        ax[j] = s_cn[i][0];
+        ay[j] = s_cn[i][1];
+        az[j] = s_cn[i][2];
+        int best = -1;
+        float bd = -INFINITY;
+        for (int p = 0; p < np0; ++p) {
+          const float d = dot3_nofma(ax[j], ay[j], az[j], s_pn[p][0], s_pn[p][1], s_pn[p][2]);
+          if (d > bd) {
+            best = p;
+            bd = d;
+          }
+        }
+        if ((best >= 0) & (bd >= cs)) {
+          atomicAdd(&s_pmem[best], 1);
+          atomicMax(&s_pkey[best], ak[j]);
+        } else {
+          un[j] = true;
+        }
+      }
+      const unsigned long long bal = __ballot(un[j]);
+      if (lane == 0) s_wcnt[j][wave] = __popcll(bal);
+    }
+    __syncthreads();  // every entry read; the counts known
+    // pack the unassigned entries to the front, in (slot, wave, lane) order
+    int u = 0;
     {
-      const int nc = s_nc;
+      int base = 0;
 #pragma unroll
-      for (int j = 0; j < kPatchVpt; ++j) {
-        const int i = j * kPatchBlock + tid;
-        live[j] = i < nc;
-        key[j] = 0ull;
-        nx[j] = ny[j] = nz[j] = 0.f;
-        if (live[j]) {
-          key[j] = s_ck[i];
-          nx[j] = s_cn[i][0];
-          ny[j] = s_cn[i][1];
-          nz[j] = s_cn[i][2];
+      for (int j = 0; j < kAsg; ++j) {
+        const unsigned long long bal = __ballot(un[j]);
+        int before = base;
+        for (int w = 0; w < wave; ++w) before += s_wcnt[j][w];
+        for (int w = 0; w < kWaves; ++w) base += s_wcnt[j][w];
+        if (un[j]) {
+          const int pos = before + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+          s_ck[pos] = ak[j];
+          s_cn[pos][0] = ax[j];
+          s_cn[pos][1] = ay[j];
+          s_cn[pos][2] = az[j];
         }
       }
+      u = base;
     }
-    // Assign, against the patches present as the batch begins.  The first
-    // patch of largest dot over all patches is the patch of largest dot
-    // among the similar ones (lowest index on ties) whenever it is similar
-    // itself, and no patch is similar otherwise.
-    const int np0 = s_np;
-#pragma unroll
-    for (int j = 0; j < kPatchVpt; ++j) {
-      if (!live[j]) continue;
-      int best = -1;
-      float bd = -INFINITY;
-      for (int p = 0; p < np0; ++p) {
-        const float d = dot3_nofma(nx[j], ny[j], nz[j], s_pn[p][0], s_pn[p][1], s_pn[p][2]);
-        if (d > bd) {
-          best = p;
-          bd = d;
-        }
-      }
-      if ((best >= 0) & (bd >= cs)) {
-        atomicAdd(&s_pmem[best], 1);
-        atomicMax(&s_pkey[best], key[j]);
-        s_ck[j * kPatchBlock + tid] = 0ull;  // assigned: out of the loop below
-      }
-    }
+    if (u == 0) continue;  // the same in every thread: nothing left for the loop
     __syncthreads();
-    // FindDeepest / BinReduce / AddPatch while candidates remain: one wave,
-    // no workgroup barrier per patch.  Each lane owns the compacted entries
-    // i = lane (mod 64) and is the only one to clear them; lane 0 writes the
-    // patch list, which the wave reads back after a wave barrier.
-    // The BinReduce pass visits every entry that is left after it, so it
-    // also finds the next FindDeepest's lane maxima: one pass per patch.
-    if (wave == 0) {
-      const int nc = s_nc;
-      int np = s_np;
-      unsigned long long mk = 0ull;
-      int mi = -1;
-      for (int i = lane; i < nc; i += 64) {
-        const unsigned long long k = s_ck[i];
-        if (k > mk) {
-          mk = k;
-          mi = i;
+    // the loop: rows r = s * kWaves + wave of the packed entries in registers
+    unsigned long long ek[kSlots];
+    float ex[kSlots], ey[kSlots], ez[kSlots];
+    unsigned long long mk = 0ull;
+    float mx = 0.f, my = 0.f, mz = 0.f;
+    const auto keep_max = [&](unsigned long long k, float x, float y, float z) {  // selects, no branch
+      const bool gt = k > mk;
+      mk = gt ? k : mk;
+      mx = gt ? x : mx;
+      my = gt ? y : my;
+      mz = gt ? z : mz;
+    };
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+      const int i = (sl * kWaves + wave) * 64 + lane;
+      ek[sl] = 0ull;
+      ex[sl] = ey[sl] = ez[sl] = 0.f;
+      if (i < u) {
+        ek[sl] = s_ck[i];
+        ex[sl] = s_cn[i][0];
+        ey[sl] = s_cn[i][1];
+        ez[sl] = s_cn[i][2];
+      }
+      keep_max(ek[sl], ex[sl], ey[sl], ez[sl]);
+    }
+    for (;;) {
+      {  // this wave's deepest remaining entry, to the exchange slot
+        const unsigned long long wbest = wave_max_u64(mk);
+        const unsigned long long own = __ballot(mk == wbest);
+        const int ol = __ffsll((long long)own) - 1;  // the owner lane (keys are unique)
+        const float wx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), ol));
+        const float wy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my), ol));
+        const float wz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mz), ol));
+        if (lane == 0) {
+          s_red[par][wave] = make_uint4((unsigned)wbest, (unsigned)(wbest >> 32), __float_as_uint(wx),
+                                        __float_as_uint(wy));
+          s_redz[par][wave] = wz;
         }
       }
-      for (;;) {
-        const unsigned long long best = wave_max_u64(mk);
-        if (best == 0ull) break;  // the same value in every lane
-        // the owner's normal, broadcast (keys are unique: one owner lane)
-        const unsigned long long own = __ballot(mk == best);
-        const int ol = __ffsll((long long)own) - 1;
-        float ox = 0.f, oy = 0.f, oz = 0.f;
-        if (mk == best) {
-          ox = s_cn[mi][0];
-          oy = s_cn[mi][1];
-          oz = s_cn[mi][2];
+      __syncthreads();
+      // FindDeepest: the deepest of the waves' (keys are unique)
+      unsigned long long best = 0ull;
+      float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const uint4 r = s_red[par][w];
+        const unsigned long long k = join64(r.x, r.y);
+        const bool gt = k > best;
+        best = gt ? k : best;
+        bx = gt ? __uint_as_float(r.z) : bx;
+        by = gt ? __uint_as_float(r.w) : by;
+        bz = gt ? s_redz[par][w] : bz;
+      }
+      if (best == 0ull) break;  // the same in every thread: the batch is done
+      // BinReduce: the deepest and every entry similar to it leave
+      int cnt = 0;
+      mk = 0ull;
+#pragma unroll
+      for (int sl = 0; sl < kSlots; ++sl) {
+        if ((sl * kWaves + wave) * 64 < u) {  // the same in every lane of the wave
+          const bool in = (ek[sl] != 0ull) & ((ek[sl] == best) | (dot3_nofma(bx, by, bz, ex[sl], ey[sl], ez[sl]) >= cs));
+          cnt += in ? 1 : 0;
+          ek[sl] = in ? 0ull : ek[sl];
+          keep_max(ek[sl], ex[sl], ey[sl], ez[sl]);
         }
-        const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ox), ol));
-        const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(oy), ol));
-        const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(oz), ol));
-        int cnt = 0;
-        mk = 0ull;
-        mi = -1;
-        for (int i = lane; i < nc; i += 64) {
-          const unsigned long long k = s_ck[i];
-          if (k == 0ull) continue;
-          if (k == best || dot3_nofma(bx, by, bz, s_cn[i][0], s_cn[i][1], s_cn[i][2]) >= cs) {
-            ++cnt;
-            s_ck[i] = 0ull;
-          } else if (k > mk) {  // remains: a candidate for the next FindDeepest
-            mk = k;
-            mi = i;
-          }
-        }
-        const int members = wave_sum_i32(cnt);
-        int slot = -1;
-        if (np < P.n_max) {
-          slot = np++;
-        } else {  // the most similar existing patch, lowest index on ties
-          float d = -__builtin_inff();
-          int pj = 0x7fffffff;
-          for (int q = lane; q < np; q += 64) {
-            const float dq = dot3_nofma(bx, by, bz, s_pn[q][0], s_pn[q][1], s_pn[q][2]);
-            if (dq > d) {  // ascending q: the first maximum stays
-              d = dq;
-              pj = q;
-            }
-          }
-          wave_argmax(d, pj);
-          if ((float)members * key_depth(best) > (float)s_pmem[pj] * key_depth(s_pkey[pj])) slot = pj;
-        }
-        if (slot >= 0 && lane == 0) {
+      }
+      if (np < P.n_max) {  // AddPatch into a free slot: the members' count by LDS atomics
+        const int slot = np++;
+        if (cnt) atomicAdd(&s_pmem[slot], cnt);
+        if (tid == 0) {
           s_pn[slot][0] = bx;
           s_pn[slot][1] = by;
           s_pn[slot][2] = bz;
           s_pkey[slot] = best;
-          s_pmem[slot] = members;
           s_pfound[slot] = (int)key_vidx(best);
         }
-        wave_lds_sync();
+      } else {  // replace the most similar existing patch (lowest index on ties) or drop
+        if (cnt) atomicAdd(&s_members[par], cnt);
+        __syncthreads();  // the member count summed; the patch list as written so far
+        const int members = s_members[par];
+        float d = -__builtin_inff();
+        int pj = 0x7fffffff;
+        for (int q = lane; q < np; q += 64) {
+          const float dq = dot3_nofma(bx, by, bz, s_pn[q][0], s_pn[q][1], s_pn[q][2]);
+          if (dq > d) {  // ascending q: the first maximum stays
+            d = dq;
+            pj = q;
+          }
+        }
+        wave_argmax(d, pj);
+        const bool take = (float)members * key_depth(best) > (float)s_pmem[pj] * key_depth(s_pkey[pj]);
+        __syncthreads();  // every thread has read the list before it changes
+        if (tid == 0) {
+          s_members[par] = 0;
+          if (take) {
+            s_pn[pj][0] = bx;
+            s_pn[pj][1] = by;
+            s_pn[pj][2] = bz;
+            s_pkey[pj] = best;
+            s_pmem[pj] = members;
+            s_pfound[pj] = (int)key_vidx(best);
+          }
+        }
       }
-      if (lane == 0) s_np = np;
+      par ^= 1;
     }
-    __syncthreads();
+    par ^= 1;
   }
+  __syncthreads();
   // the patch list, each with its deepest member's record
-  const int np = s_np;
   if (tid == 0) P.count[e] = np;
   const long long S = (long long)A.n_env * P.n_max;
-  for (int p = tid; p < P.n_max; p += kPatchBlock) {
+  for (int p = tid; p < P.n_max; p += kPatchThreads) {
     const long long s = (long long)e * P.n_max + p;
     if (p < np) {
       const unsigned v = key_vidx(s_pkey[p]);
@@ -307,7 +374,7 @@ template <int DT, int LAYOUT>
 hipError_t patches_launch(const FwdArgs& a, const PatchArgs& p, hipStream_t s) {
   hipError_t e = mark(false, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_patches<DT, LAYOUT>), dim3(a.n_env), dim3(kPatchBlock), 0, s, a, p);
+  hipLaunchKernelGGL((k_patches<DT, LAYOUT>), dim3(a.n_env), dim3(kPatchThreads), 0, s, a, p);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return mark(true, s);
