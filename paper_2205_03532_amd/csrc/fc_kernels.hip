@@ -674,10 +674,18 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     for (int j = 0; j < V; ++j) s_accv[j][0][tid] = s_accv[j][1][tid] = s_accv[j][2][tid] = make_float2(0.f, 0.f);
   }
 
-  // R, t and the upstream weight of the chunk's envs, computed once per item
+  // R, t and the upstream weight of the chunk's envs, computed once per
+  // item, with the env ids and the rows they write: read from LDS in the env
+  // loop, a global load there would wait for every corner load in flight
   __shared__ float4 s_pose[kBwdChunkMax][4];
+  __shared__ int s_env[kBwdChunkMax];
+  __shared__ int s_row[kBwdChunkMax];
+  __shared__ long long s_qoff[kBwdChunkMax];
   if (tid < ch.len) {
     const int e = A.env_list[ch.first + tid];
+    s_env[tid] = e;
+    s_row[tid] = A.env_tile_base[e] + it.tile_in_mesh;
+    s_qoff[tid] = A.envs[e].qoff;
     const Rigid P = load_pose(A.pose, A.n_env, e);
     s_pose[tid][0] = make_float4(P.r00, P.r01, P.r02, P.tx);
     s_pose[tid][1] = make_float4(P.r10, P.r11, P.r12, P.ty);
@@ -718,7 +726,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
       if (sum == kProbeSentinel) A.loss[0] = sum;
       return;
     }
-    const int e = A.env_list[ch.first + c];
+    const int e = s_env[c];
     const Cell* cl = S.cl;
     const auto& cc = S.cc;
     if constexpr (!ADJ) {  // the forward's candidates, bins and per-bin maxima only
@@ -797,7 +805,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
         }
       }
       if (A.per_env && A.d_verts && ok[j]) {
-        const long long q = A.envs[e].qoff + it.vstart + j * kBwdBlock + tid;
+        const long long q = s_qoff[c] + it.vstart + j * kBwdBlock + tid;
         A.d_verts[q] = dvx;
         A.d_verts[A.Q + q] = dvy;
         A.d_verts[2 * A.Q + q] = dvz;
@@ -828,7 +836,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
       red = wave_sum8(acc);
     }
     if (lane < 8)
-      A.pose_part[((long long)(A.env_tile_base[e] + it.tile_in_mesh) * NW + wave) * 8 + wave_sum8_slot(lane)] = red;
+      A.pose_part[((long long)s_row[c] * NW + wave) * 8 + wave_sum8_slot(lane)] = red;
   };
   if constexpr (V <= 2) {
     Stage SA, SB;
