@@ -256,24 +256,15 @@ __device__ __forceinline__ int argmax_bin(const float* __restrict__ dirs, int K,
 // face, the other two components divided by it give (u, v) in [-1, 1].
 __device__ __forceinline__ int cube_cell(float nx, float ny, float nz) {
   const float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
-  int face;
-  float u, v, m;
-  if ((ax >= ay) & (ax >= az)) {
-    face = nx >= 0.f ? 0 : 1;
-    u = ny;
-    v = nz;
-    m = ax;
-  } else if (ay >= az) {
-    face = ny >= 0.f ? 2 : 3;
-    u = nx;
-    v = nz;
-    m = ay;
-  } else {
-    face = nz >= 0.f ? 4 : 5;
-    u = nx;
-    v = ny;
-    m = az;
-  }
+  // x face if x dominates, else y if y dominates z, else z (selects, no branches)
+  const bool fx = (ax >= ay) & (ax >= az);
+  const bool fy = !fx & (ay >= az);
+  const int axis = fx ? 0 : (fy ? 1 : 2);
+  const float comp = fx ? nx : (fy ? ny : nz);
+  const int face = 2 * axis + (comp >= 0.f ? 0 : 1);
+  const float u = fx ? ny : nx;
+  const float v = (fx | fy) ? nz : ny;
+  const float m = fx ? ax : (fy ? ay : az);
   // hardware reciprocal (1 ulp): the table's cones carry a 1e-4 rad margin
   // for the cell choice, far above this rounding
   const float s = (0.5f * kLutN) * __builtin_amdgcn_rcpf(m);
@@ -299,16 +290,32 @@ __device__ __forceinline__ int argmax_bin_lut(const BinCell* __restrict__ lut, c
   int bin = (int)((w[0] >> 8) & 0xffu);
   float4 d = dir4[bin];
   float best = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
+  // entries 1..kLutEager - 1 for every lane, kept only where the list has
+  // them (an absent entry reads byte 0, bin 0, and is never taken); the
+  // rest, which few cells have, behind a branch the wavefront takes together
+  constexpr int kLutEager = 4;
 #pragma unroll
-  for (int i = 1; i < kLutMax; ++i) {
-    if (i < n) {
-      const int b = i + 1;  // byte of k[i]
-      const int k = (int)((w[b >> 2] >> ((b & 3) * 8)) & 0xffu);
-      d = dir4[k];
-      const float v = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
-      if (v > best) {
-        best = v;
-        bin = k;
+  for (int i = 1; i < kLutEager; ++i) {
+    const int b = i + 1;  // byte of k[i]
+    const int k = (int)((w[b >> 2] >> ((b & 3) * 8)) & 0xffu);
+    d = dir4[k];
+    const float v = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
+    const bool take = (i < n) & (v > best);
+    best = take ? v : best;
+    bin = take ? k : bin;
+  }
+  if (__ballot(n > kLutEager) != 0ull) {
+#pragma unroll
+    for (int i = kLutEager; i < kLutMax; ++i) {
+      if (i < n) {
+        const int b = i + 1;
+        const int k = (int)((w[b >> 2] >> ((b & 3) * 8)) & 0xffu);
+        d = dir4[k];
+        const float v = fmaf(nz, d.z, fmaf(ny, d.y, nx * d.x));
+        if (v > best) {
+          best = v;
+          bin = k;
+        }
       }
     }
   }

@@ -623,6 +623,35 @@ __device__ __forceinline__ float2 wave_sum8(const float2 a[8]) {
   return ncombine(x, xor32_pair(x));
 }
 
+// Per-wavefront bin keys in LDS, kKeyCopies copies: lane l updates copy
+// l mod kKeyCopies, so lanes that share a bin (a flat face puts a whole
+// wavefront in one) spread their atomics over kKeyCopies addresses in
+// different banks instead of queueing on one.  The flush takes the largest
+// of a bin's copies, clears them and issues one global atomic per non-empty
+// bin.
+constexpr int kKeyCopies = 4;
+constexpr int kKeyStride = FC_MAX_BINS + 1;  // odd stride: the copies of a bin sit in different banks
+__device__ __forceinline__ void wave_key_max(unsigned long long* s_wkeys, int bin, unsigned long long key) {
+  atomicMax(&s_wkeys[(__lane_id() & (kKeyCopies - 1)) * kKeyStride + bin], key);
+}
+__device__ __forceinline__ void wave_key_flush(unsigned long long* s_wkeys, unsigned long long* keys, int K) {
+  wave_lds_sync();  // the lanes' LDS atomics before the per-bin reads
+  const int lane = __lane_id();
+  if (lane < K) {
+    unsigned long long kk = 0ull;
+#pragma unroll
+    for (int c = 0; c < kKeyCopies; ++c) {
+      const unsigned long long v = s_wkeys[c * kKeyStride + lane];
+      kk = v > kk ? v : kk;
+    }
+    if (kk) {
+      atomicMax(&keys[lane], kk);
+#pragma unroll
+      for (int c = 0; c < kKeyCopies; ++c) s_wkeys[c * kKeyStride + lane] = 0ull;
+    }
+  }
+}
+
 struct NoQuery {};
 // Measurement mode: the same items, loop and loads, and no arithmetic beyond
 // summing the corners (kept live by a store that a sentinel sum would take).
@@ -634,7 +663,12 @@ constexpr float kProbeSentinel = -1.5e38f;
 // forward's candidates and per-bin maxima (one gather serves both): each
 // wavefront keeps its own K keys in LDS, flushed to the env's global keys
 // after every env.
-template <int DT, int LAYOUT, class QX, bool ADJ = true>
+// PERV: per-env vertex gradients (A.per_env), stored per query; otherwise the
+// shared vertex gradient is summed in LDS.  A compile-time choice keeps the
+// stores of the other mode out of the env loop, where any vector-memory
+// operation the compiler cannot count ahead makes it wait for the corner
+// loads in flight.
+template <int DT, int LAYOUT, class QX, bool ADJ = true, bool PERV = false>
 __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, unsigned long long* s_wkeys,
                                               const BinCell* s_lut, const float4* s_dir4) {
   constexpr bool PROBE = __is_same(QX, GatherOnly);
@@ -654,7 +688,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
   const GridDev& g = A.grids[it.gm & 0xff];
   const MeshDev& m = A.meshes[it.gm >> 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool shared_v = (A.d_verts != nullptr) && !A.per_env;
+  const bool shared_v = !PERV && (A.d_verts != nullptr);
 
   float vx[V], vy[V], vz[V];
   bool ok[V];
@@ -738,17 +772,10 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
           float nx, ny, nz;
           normalize(gx, gy, gz, nx, ny, nz);
           const int bin = argmax_bin_lut(s_lut, s_dir4, F.dirs, F.K, nx, ny, nz);
-          atomicMax(&s_wkeys[bin], make_key(-phi, (unsigned)(it.vstart + j * kBwdBlock + tid)));
+          wave_key_max(s_wkeys, bin, make_key(-phi, (unsigned)(it.vstart + j * kBwdBlock + tid)));
         }
       }
-      wave_lds_sync();  // the lanes' LDS atomics before the per-bin reads
-      if (lane < F.K) {
-        const unsigned long long kk = s_wkeys[lane];
-        if (kk) {
-          atomicMax(&F.keys[(long long)e * F.K + lane], kk);
-          s_wkeys[lane] = 0ull;
-        }
-      }
+      wave_key_flush(s_wkeys, F.keys + (long long)e * F.K, F.K);
       return;
     }
     const Rigid P = pose_of(c);
@@ -768,7 +795,7 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
           float nx, ny, nz;
           normalize(gx, gy, gz, nx, ny, nz);
           const int bin = argmax_bin_lut(s_lut, s_dir4, F.dirs, F.K, nx, ny, nz);
-          atomicMax(&s_wkeys[bin], make_key(-phi, (unsigned)(it.vstart + j * kBwdBlock + tid)));
+          wave_key_max(s_wkeys, bin, make_key(-phi, (unsigned)(it.vstart + j * kBwdBlock + tid)));
         }
       }
       const bool act = ok[j] & cl[j].inside & (phi < 0.f);
@@ -804,23 +831,14 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
           s_accv[j][2][tid] = a2;
         }
       }
-      if (A.per_env && A.d_verts && ok[j]) {
+      if (PERV && ok[j]) {  // launched with PERV only when A.d_verts is set
         const long long q = s_qoff[c] + it.vstart + j * kBwdBlock + tid;
         A.d_verts[q] = dvx;
         A.d_verts[A.Q + q] = dvy;
         A.d_verts[2 * A.Q + q] = dvz;
       }
     }
-    if constexpr (QUERY) {
-      wave_lds_sync();  // the lanes' LDS atomics before the per-bin reads
-      if (lane < F.K) {
-        const unsigned long long kk = s_wkeys[lane];
-        if (kk) {
-          atomicMax(&F.keys[(long long)e * F.K + lane], kk);
-          s_wkeys[lane] = 0ull;
-        }
-      }
-    }
+    if constexpr (QUERY) wave_key_flush(s_wkeys, F.keys + (long long)e * F.K, F.K);
     // fixed-shape reduction within the wavefront; one partial row of eight
     // pairs (the last one zero) per (env, tile, wave), no workgroup barrier
     float2 red = make_float2(0.f, 0.f);
@@ -869,9 +887,9 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
   }
 }
 
-template <int DT, int LAYOUT>
+template <int DT, int LAYOUT, bool PERV>
 __global__ __launch_bounds__(kBwdBlock) void k_backward(BwdArgs A) {
-  backward_item<DT, LAYOUT>(A, NoQuery{}, nullptr, nullptr, nullptr);
+  backward_item<DT, LAYOUT, NoQuery, true, PERV>(A, NoQuery{}, nullptr, nullptr, nullptr);
 }
 
 template <int DT, int LAYOUT>
@@ -882,11 +900,11 @@ __global__ __launch_bounds__(kBwdBlock) void k_gather_probe(BwdArgs A) {
 // Query and adjoint in one pass (ADJ), or the query alone on the same work
 // items (the forward's env-chunked mode): the bin-search tables go to LDS as
 // in k_forward, plus K keys per wavefront.
-template <int DT, int LAYOUT, bool ADJ>
+template <int DT, int LAYOUT, bool ADJ, bool PERV = false>
 __device__ __forceinline__ void query_chunked_body(const BwdArgs& A, const QueryExtra& F) {
   __shared__ BinCell s_lut[kLutCells];
   __shared__ float4 s_dir4[FC_MAX_BINS];
-  __shared__ unsigned long long s_keys[kBwdBlock / 64][FC_MAX_BINS];
+  __shared__ unsigned long long s_keys[kBwdBlock / 64][kKeyCopies * kKeyStride];
   static_assert(sizeof(BinCell) == sizeof(uint4), "BinCell is one 16-byte load");
   static_assert(FC_MAX_BINS == 64, "one key slot per lane");
   const uint4* src = reinterpret_cast<const uint4*>(F.bin_lut);
@@ -896,14 +914,14 @@ __device__ __forceinline__ void query_chunked_body(const BwdArgs& A, const Query
     const int k = threadIdx.x < F.K ? threadIdx.x : 0;
     s_dir4[threadIdx.x] = make_float4(F.dirs[k], F.dirs[F.K + k], F.dirs[2 * F.K + k], 0.f);
   }
-  s_keys[threadIdx.x >> 6][threadIdx.x & 63] = 0ull;
+  for (int i = threadIdx.x & 63; i < kKeyCopies * kKeyStride; i += 64) s_keys[threadIdx.x >> 6][i] = 0ull;
   __syncthreads();
-  backward_item<DT, LAYOUT, QueryExtra, ADJ>(A, F, s_keys[threadIdx.x >> 6], s_lut, s_dir4);
+  backward_item<DT, LAYOUT, QueryExtra, ADJ, PERV>(A, F, s_keys[threadIdx.x >> 6], s_lut, s_dir4);
 }
 
-template <int DT, int LAYOUT>
+template <int DT, int LAYOUT, bool PERV>
 __global__ __launch_bounds__(kBwdBlock) void k_query_backward(BwdArgs A, QueryExtra F) {
-  query_chunked_body<DT, LAYOUT, true>(A, F);
+  query_chunked_body<DT, LAYOUT, true, PERV>(A, F);
 }
 
 template <int DT, int LAYOUT>
@@ -1166,7 +1184,10 @@ template <int DT, int LAYOUT>
 hipError_t bwd_launch(const BwdArgs& a, hipStream_t s) {
   hipError_t e = mark(false, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_backward<DT, LAYOUT>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a);
+  if (a.per_env && a.d_verts)  // per-env vertex gradients are stored
+    hipLaunchKernelGGL((k_backward<DT, LAYOUT, true>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_backward<DT, LAYOUT, false>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = mark(true, s);
@@ -1178,7 +1199,10 @@ template <int DT, int LAYOUT>
 hipError_t qbwd_launch(const BwdArgs& a, const QueryExtra& q, const FwdArgs& f, hipStream_t s) {
   hipError_t e = mark(false, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_query_backward<DT, LAYOUT>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a, q);
+  if (a.per_env && a.d_verts)  // per-env vertex gradients are stored
+    hipLaunchKernelGGL((k_query_backward<DT, LAYOUT, true>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a, q);
+  else
+    hipLaunchKernelGGL((k_query_backward<DT, LAYOUT, false>), dim3(bwd_grid(a)), dim3(kBwdBlock), 0, s, a, q);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = mark(true, s);
@@ -1256,13 +1280,21 @@ hipError_t bwd_dtype(const BwdArgs& a, int dtype, int layout, hipStream_t s) {
 
 }  // namespace
 
+// the lowest over both vertex-gradient modes, so the chunk (which orders the
+// shared vertex sums) does not depend on the mode of a call
 template <int DT, int LAYOUT>
 int bwd_occupancy() {
-  int a = 0, b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_backward<DT, LAYOUT>, kBwdBlock, 0) != hipSuccess) a = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_query_backward<DT, LAYOUT>, kBwdBlock, 0) != hipSuccess)
-    b = 1;
-  return std::max(1, std::min(a, b));
+  int r = 1 << 20;
+  const auto take = [&r](const void* k) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kBwdBlock, 0) != hipSuccess) n = 1;
+    r = std::min(r, n);
+  };
+  take(reinterpret_cast<const void*>(k_backward<DT, LAYOUT, false>));
+  take(reinterpret_cast<const void*>(k_backward<DT, LAYOUT, true>));
+  take(reinterpret_cast<const void*>(k_query_backward<DT, LAYOUT, false>));
+  take(reinterpret_cast<const void*>(k_query_backward<DT, LAYOUT, true>));
+  return std::max(1, r);
 }
 
 template <int DT>
