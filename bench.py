@@ -447,6 +447,8 @@ def measure_nutbolt_1024(device, n, warmup):
     """Forward plus backward on 1,024 nut-bolt envs (the differentiation
     configuration; its gradients are checked against FP64 finite differences
     on 64 envs by the parity tests)."""
+    import torch
+
     from paper_2205_03532_amd import fc
     from paper_2205_03532_amd import workloads as W
 
@@ -458,11 +460,15 @@ def measure_nutbolt_1024(device, n, warmup):
     ms_sep = time_calls(lambda: (fc.fc_sdf_query(b, pose, fused_out=o),
                                  fc.fc_sdf_query_backward(b, pose, K_PENALTY, g)), n, warmup)
     rl = step_roofline(b, pose, n, warmup, alg_bytes_per_query("f32"))
+    cand = b.new_candidates()
+    fc.fc_sdf_query(b, pose, cand=cand)
+    torch.cuda.synchronize()
+    err = contact_errors(w, cand, [0, 1, 2, 3])
     return {"workload": f"nut-on-bolt, {w.n_env} envs x {w.meshes[0].n} vertices, 256x256x512 FP32 bolt SDF, "
                         "penalty 0.5 k depth^2 (k = 1e4), gradients for pose twists and shared vertices",
             "queries_per_step": b.Q, "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3),
             "separate_fwd_then_bwd_queries_per_s": b.Q / (ms_sep * 1e-3), "call_ms": ms_one,
-            "roofline": rl, "launch": b.get_launch()}
+            "errors_vs_fp64_oracle": err, "roofline": rl, "launch": b.get_launch()}
 
 
 def measure_forms(w32, device, n, warmup):
@@ -526,15 +532,19 @@ def measure_forms(w32, device, n, warmup):
     g_fwd = fc.fc_graph_create(b, pose, fused_out=o)
     ms_one = time_calls(g_one.launch, n, warmup)
     ms_fwd = time_calls(g_fwd.launch, n, warmup)
+    envs = sample_envs_per_type(wm, 2, seed=3)
+    cand = b.new_candidates()
+    fc.fc_sdf_query(b, pose, cand=cand)
+    torch.cuda.synchronize()
     out["mixed_4096_envs_5_types_graph"] = {
         "fwd_bwd_queries_per_s": b.Q / (ms_one * 1e-3), "fwd_queries_per_s": b.Q / (ms_fwd * 1e-3),
         "queries_per_step": b.Q, "launch": b.get_launch(),
+        "errors_vs_fp64_oracle": contact_errors(wm, cand, envs),
         "roofline": step_roofline(b, pose, n, warmup, alg_bytes_per_query("f32"))}
-    del b, o, g, g_one, g_fwd
+    del b, o, g, g_one, g_fwd, cand
     # the same uneven batch with every grid in FP16, then BF16: depth and normal
     # error against the FP64 oracle on the FP32 grids over all contacts of two
     # sampled envs per part type
-    envs = sample_envs_per_type(wm, 2, seed=3)
     for dt in ("f16", "bf16"):
         wh = W.half_storage(wm, dt)
         b = make_batch(wh, device)
