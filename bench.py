@@ -113,13 +113,19 @@ def measured_traffic(kernel):
 
 
 def make_batch(w, device, layout=None, launch=None):
-    """The bench's batch: envs scheduled in spatial order, the tuned launch shape
-    (autotune cache entry for this signature if present, else BENCH_LAUNCH)."""
-    from paper_2205_03532_amd import fc
+    """The bench's batch: envs scheduled in spatial order, the tuned layout
+    (when no layout is asked for and the autotune cache records one for this
+    batch, else BENCH_LAYOUT) and the tuned launch shape (cache entry for the
+    signature if present, else BENCH_LAUNCH)."""
+    from paper_2205_03532_amd import autotune, fc
 
     if os.path.exists(TUNE_CACHE):
         fc.fc_autotune_load(TUNE_CACHE)
     b = fc.Batch.from_workload(w, device=device, layout=layout or BENCH_LAYOUT, env_order=fc.locality_order(w))
+    tuned = autotune.best_layout(b.signature(), TUNE_CACHE) if layout is None else None
+    if tuned is not None and tuned != b.layout:
+        del b
+        b = fc.Batch.from_workload(w, device=device, layout=tuned, env_order=fc.locality_order(w))
     cached = os.path.exists(TUNE_CACHE) and any(e["key"] == b.signature()
                                                  for e in json.load(open(TUNE_CACHE))["entries"])
     if launch is not None or not cached:
@@ -711,7 +717,8 @@ def main():
     kname, kkey = "k_query_backward (one-pass query, reduction and penalty adjoint)", "k_query_backward"
     kms = float(k_one.mean())  # the main kernel alone, mean over the timed launches
     achieved = bpq * Q / (kms * 1e-3) / 1e9
-    traffic = measured_traffic(kkey) if (args.layout or BENCH_LAYOUT) == BENCH_LAYOUT and args.dtype == "f32" else None
+    # the counters were taken on the FP32 brick layout
+    traffic = measured_traffic(kkey) if batch.layout == "brick" and args.dtype == "f32" else None
 
     # accuracy of the timed configuration on a sample (outside the timed region)
     cand = batch.new_candidates()
@@ -740,7 +747,7 @@ def main():
                         f"adjoint (k = 1e4, shared vertex gradients)",
             "n_env": w.n_env,
             "queries_per_step": Q,
-            "layout": args.layout or BENCH_LAYOUT,
+            "layout": batch.layout,
             "env_order": "spatial (locality_order)",
             "launch": launch,
         },

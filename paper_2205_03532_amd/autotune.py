@@ -15,6 +15,23 @@ records the fastest in a JSON cache keyed by the batch signature:
 matching signature start from that shape.
 
     python -m paper_2205_03532_amd.autotune --workload nutbolt --out tune.json
+
+With ``--layouts`` it also chooses the grid layout (the brick shape: 4x4x4-node
+bricks, 4x4x2-node slabs, or the plain linear grid).  Layouts only move
+samples, so every output of the one-pass step (contacts, loss, pose and vertex
+gradients) must be bit-identical across them: the adjoint's sums run in an
+order fixed by the vertex tile, the block and the env chunk, and the chunk is
+chosen from the device's resident capacity over all layouts, never per
+layout.  The tuner checks that identity and records the layout with the
+fastest one-pass step (brick unless another is more than 1 % faster) under
+a layout-free key:
+
+    {"layouts": [{"key": "<signature without lay=>", "layout": "brick",
+                  "step_ms": {"brick": 0.13, "slab": 0.14, "linear": 0.21}}]}
+
+The one-pass kernel's own tile (vertices per item) and block are not tuned:
+they order every per-env sum of the adjoint, so a different choice would
+change the gradients' rounding.
 """
 from __future__ import annotations
 
@@ -46,7 +63,8 @@ def candidate_shapes():
 
 
 def _snapshot(out):
-    return {k: v.detach().cpu().numpy().copy() for k, v in out.items()}
+    """Host copies of the tensors of an output dict (flags and None skipped)."""
+    return {k: v.detach().cpu().numpy().copy() for k, v in out.items() if hasattr(v, "detach")}
 
 
 def _same(a, b):
@@ -91,15 +109,108 @@ def tune(batch, pose, shapes=None, reps=10, warmup=3, log=print):
     return dict(best, key=batch.signature()), results
 
 
-def save(entries, path):
-    old = []
+def _load(path):
     if os.path.exists(path):
         with open(path) as f:
-            old = json.load(f).get("entries", [])
-    keys = {e["key"] for e in entries}
-    merged = [e for e in old if e["key"] not in keys] + entries
+            return json.load(f)
+    return {}
+
+
+def _merge(old, new):
+    keys = {e["key"] for e in new}
+    return [e for e in old if e["key"] not in keys] + new
+
+
+def save(entries, path, layouts=()):
+    """Merge launch-shape entries and layout entries into the cache at path
+    (an entry replaces the one with the same key)."""
+    rec = _load(path)
+    rec["entries"] = _merge(rec.get("entries", []), list(entries))
+    if layouts or rec.get("layouts"):
+        rec["layouts"] = _merge(rec.get("layouts", []), list(layouts))
     with open(path, "w") as f:
-        json.dump({"entries": merged}, f, indent=1)
+        json.dump(rec, f, indent=1)
+
+
+# Dense layouts of the same samples: the same results, bit for bit.  The
+# sparse layout is a footprint choice (other values in bricks it does not
+# store), not a speed choice, so it is never picked here.  The first is the
+# default; another replaces it only when faster by more than LAYOUT_MARGIN
+# (about the run-to-run spread of these timings), so noise does not flip it.
+LAYOUTS = ("brick", "slab", "linear")
+LAYOUT_MARGIN = 0.01
+
+
+def pick_layout(step_ms):
+    """The default layout unless another's step is faster by more than
+    LAYOUT_MARGIN; then the fastest."""
+    fastest = min(step_ms, key=step_ms.get)
+    return fastest if step_ms[fastest] < (1.0 - LAYOUT_MARGIN) * step_ms[LAYOUTS[0]] else LAYOUTS[0]
+
+
+def layout_key(signature):
+    """A batch signature without its layout: the key of a layout entry."""
+    return ";".join(f for f in signature.split(";") if not f.startswith("lay="))
+
+
+def best_layout(signature, path):
+    """The layout the cache at path records for a batch with this signature
+    (of any layout), or None."""
+    key = layout_key(signature)
+    for e in _load(path).get("layouts", []):
+        if e["key"] == key:
+            return e["layout"]
+    return None
+
+
+def _step_snapshot(batch, pose, k):
+    import torch
+
+    o, g = batch.new_contacts(), batch.new_grads(per_env=False)
+    fc.fc_sdf_query_and_backward(batch, pose, o, k, g)
+    torch.cuda.synchronize()
+    return {**{"c_" + n: v for n, v in _snapshot(o).items()}, **{"g_" + n: v for n, v in _snapshot(g).items()}}
+
+
+def time_step(batch, pose, k, reps, warmup):
+    """Median one-pass step (fc_sdf_query_and_backward) in ms, HIP events on
+    the current stream."""
+    import torch
+
+    o, g = batch.new_contacts(), batch.new_grads(per_env=False)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fc.fc_sdf_query_and_backward(batch, pose, o, k, g)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fc.fc_sdf_query_and_backward(batch, pose, o, k, g)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def tune_layouts(w, layouts=LAYOUTS, k=1e4, reps=10, warmup=3, device="cuda:0", shapes=None, log=print):
+    """Per layout: a batch in spatial env order, its forward launch shape
+    tuned, its one-pass step timed; every layout's step outputs must equal the
+    first layout's bit for bit.  Returns (layout entry, launch entries)."""
+    pose = fc.pose_tensor(w.pose, device)
+    ref, step_ms, entries, sig = None, {}, [], None
+    for lay in layouts:
+        batch = fc.Batch.from_workload(w, device=device, layout=lay, env_order=fc.locality_order(w))
+        best, _ = tune(batch, pose, shapes=shapes, reps=reps, warmup=warmup, log=lambda s: None)
+        entries.append(best)
+        snap = _step_snapshot(batch, pose, k)
+        if ref is None:
+            ref = snap
+        elif not _same(snap, ref):
+            bad = [n for n in ref if not np.array_equal(snap[n].view(np.uint8), ref[n].view(np.uint8))]
+            raise RuntimeError(f"layout {lay} changed the step's outputs: {bad}")
+        step_ms[lay] = time_step(batch, pose, k, reps, warmup)
+        sig = batch.signature()
+        log(f"  {lay}: forward {best['ms']:.4f} ms ({ {n: best[n] for n in DEFAULT} }), step {step_ms[lay]:.4f} ms")
+        del batch
+    return dict(key=layout_key(sig), layout=pick_layout(step_ms), step_ms=step_ms), entries
 
 
 def _workload(name, dtype):
@@ -121,10 +232,18 @@ def main(argv=None):
     ap.add_argument("--workload", default="nutbolt", choices=["nutbolt", "mixed", "torus"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--layout", default="brick", choices=["linear", "brick", "slab", "sparse"])
+    ap.add_argument("--layouts", action="store_true",
+                    help="also choose the dense layout (brick, slab, linear) by the one-pass step's time")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     w = _workload(a.workload, a.dtype)
+    if a.layouts:
+        print(f"tuning the layout of {w.name} ({a.dtype})", flush=True)
+        lay, entries = tune_layouts(w, reps=a.reps, log=lambda s: print(s, flush=True))
+        save(entries, a.out, [lay])
+        print(json.dumps(lay), flush=True)
+        return 0
     batch = fc.Batch.from_workload(w, layout=a.layout, env_order=fc.locality_order(w))
     pose = fc.pose_tensor(w.pose)
     print(f"tuning {w.name} ({a.dtype}, {a.layout}): {batch.Q} queries", flush=True)

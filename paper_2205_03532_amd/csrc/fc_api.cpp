@@ -549,7 +549,7 @@ fc_status build_backward_tables(fc_batch* b) {
     const int e = b->order[oi];
     groups[(size_t)b->env_mesh[e] * ng + b->env_grid[e]].push_back(e);
   }
-  b->bwd_chunk = choose_bwd_chunk(b, groups, b->num_cus * backward_blocks_per_cu(b->dtype, b->layout));
+  b->bwd_chunk = choose_bwd_chunk(b, groups, b->num_cus * backward_blocks_per_cu(b->dtype));
   const size_t chunk = (size_t)b->bwd_chunk;
   long long vpart = 0;
   long long voff = 0;

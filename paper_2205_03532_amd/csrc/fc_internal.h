@@ -13,8 +13,9 @@ namespace fcimpl {
 // per-env sum of the adjoint, so they are constants, never tuned.  The chunk
 // (envs per item, which orders the shared vertex sums) is chosen once per
 // batch at creation from the batch's shape and the device's resident
-// capacity (choose_bwd_chunk): the gradients are bit-identical for every
-// launch shape and call of a batch.
+// capacity (choose_bwd_chunk), the same for every grid layout: the gradients
+// are bit-identical for every launch shape and call of a batch, and across
+// layouts of the same samples.
 constexpr int kBwdTile = 512;     // vertices per backward item (pose partial sums)
 constexpr int kBwdBlock = 256;    // threads per backward workgroup (2 vertices each)
 constexpr int kBwdChunkMin = 4;   // environments per backward item, at least ...
@@ -257,6 +258,6 @@ hipError_t launch_to_bricks(const void* src, void* dst, int elem, int layout, in
 bool forward_shape_supported(int block, int vpt);
 // workgroups of k_backward and of k_query_backward (the lower) that can be
 // resident on one compute unit at once, for a grid of dtype and layout
-int backward_blocks_per_cu(int dtype, int layout);
+int backward_blocks_per_cu(int dtype);
 
 }  // namespace fcimpl

@@ -1297,19 +1297,19 @@ int bwd_occupancy() {
   return std::max(1, r);
 }
 
+// ... and the lowest over the layouts, so that it does not depend on the
+// layout either: every layout of the same samples gives the same bits
 template <int DT>
-int bwd_occupancy_layout(int layout) {
-  if (layout == FC_LAYOUT_BRICK) return bwd_occupancy<DT, FC_LAYOUT_BRICK>();
-  if (layout == FC_LAYOUT_SLAB) return bwd_occupancy<DT, FC_LAYOUT_SLAB>();
-  if (layout == FC_LAYOUT_SPARSE) return bwd_occupancy<DT, FC_LAYOUT_SPARSE>();
-  return bwd_occupancy<DT, FC_LAYOUT_LINEAR>();
+int bwd_occupancy_all_layouts() {
+  return std::min(std::min(bwd_occupancy<DT, FC_LAYOUT_LINEAR>(), bwd_occupancy<DT, FC_LAYOUT_BRICK>()),
+                  std::min(bwd_occupancy<DT, FC_LAYOUT_SLAB>(), bwd_occupancy<DT, FC_LAYOUT_SPARSE>()));
 }
 
-int backward_blocks_per_cu(int dtype, int layout) {
+int backward_blocks_per_cu(int dtype) {
   switch (dtype) {
-    case kF32: return bwd_occupancy_layout<kF32>(layout);
-    case kF16: return bwd_occupancy_layout<kF16>(layout);
-    case kBF16: return bwd_occupancy_layout<kBF16>(layout);
+    case kF32: return bwd_occupancy_all_layouts<kF32>();
+    case kF16: return bwd_occupancy_all_layouts<kF16>();
+    case kBF16: return bwd_occupancy_all_layouts<kBF16>();
   }
   return 1;
 }

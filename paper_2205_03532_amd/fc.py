@@ -275,6 +275,7 @@ class Batch:
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
+        self.layout = layout
         self.n_env = int(len(env_grid))
         self.K = int(bins.shape[1])
         self._keep = []

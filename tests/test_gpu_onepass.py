@@ -194,3 +194,19 @@ def test_gather_probe_writes_nothing_and_is_timed():
     assert list(kid) == [fc.FC_KERNEL_GATHER_PROBE] * 2 and np.all(ms > 0)
     assert torch.equal(sink, torch.full((4,), 7.0, device="cuda"))
     assert torch.equal(b.workspace, ws_before)
+
+
+def test_layout_tuner_steps_are_bit_identical_across_layouts():
+    """The layout tuner on a mixed batch (five grids, five meshes' shared
+    vertex gradients): brick, slab and linear give the same contacts, loss,
+    twists and vertex gradients bit for bit (the tuner raises otherwise), and
+    it records the fastest under the layout-free key."""
+    torch_gpu()
+    from paper_2205_03532_amd import autotune
+
+    w = W.subset(W.mixed_workload(), range(60))
+    lay, entries = autotune.tune_layouts(w, reps=3, warmup=1, shapes=[autotune.DEFAULT], log=print)
+    assert set(lay["step_ms"]) == set(autotune.LAYOUTS)
+    assert lay["layout"] == autotune.pick_layout(lay["step_ms"])
+    assert len(entries) == len(autotune.LAYOUTS) and len({e["key"] for e in entries}) == len(autotune.LAYOUTS)
+    assert {autotune.layout_key(e["key"]) for e in entries} == {lay["key"]}

@@ -31,6 +31,38 @@ def test_cache_save_merges_by_key(tmp_path):
     assert [x["ms"] for x in e if x["key"] == "a"] == [0.5]
 
 
+def test_layout_entries_are_keyed_without_the_layout(tmp_path):
+    p = str(tmp_path / "c.json")
+    sig = "v1;dt=0;lay=1;K=32;env=1000;grids=256x256x512,;meshes=16396,"
+    assert autotune.layout_key(sig) == "v1;dt=0;K=32;env=1000;grids=256x256x512,;meshes=16396,"
+    assert autotune.best_layout(sig, p) is None  # no cache yet
+    lay = dict(key=autotune.layout_key(sig), layout="slab", step_ms={"brick": 0.2, "slab": 0.1})
+    autotune.save([dict(autotune.DEFAULT, key=sig, ms=1.0)], p, [lay])
+    # any layout's signature of the same batch finds the entry; another batch does not
+    assert autotune.best_layout(sig.replace("lay=1", "lay=0"), p) == "slab"
+    assert autotune.best_layout(sig.replace("env=1000", "env=999"), p) is None
+    # launch-shape saves keep the layout entries; a layout save replaces by key
+    autotune.save([dict(autotune.DEFAULT, key="b", ms=1.0)], p)
+    autotune.save([], p, [dict(lay, layout="brick")])
+    rec = json.load(open(p))
+    assert [e["layout"] for e in rec["layouts"]] == ["brick"]
+    assert sorted(e["key"] for e in rec["entries"]) == sorted([sig, "b"])
+
+
+def test_layout_choice_keeps_brick_within_the_margin():
+    assert autotune.pick_layout({"brick": 1.0, "slab": 0.995, "linear": 2.0}) == "brick"
+    assert autotune.pick_layout({"brick": 1.0, "slab": 0.98, "linear": 0.985}) == "slab"
+    assert autotune.pick_layout({"brick": 1.0, "slab": 1.2, "linear": 0.5}) == "linear"
+
+
+def test_library_reads_a_cache_with_layout_entries(tmp_path):
+    L = fc.lib()
+    p = str(tmp_path / "c.json")
+    autotune.save([dict(autotune.DEFAULT, key="a", ms=1.0), dict(autotune.DEFAULT, key="b", ms=2.0)], p,
+                  [dict(key="a", layout="brick", step_ms={"brick": 0.1, "slab": 0.2})])
+    assert L.fc_autotune_load(p.encode()) == 2
+
+
 def test_locality_order_is_a_permutation_grouped_by_type():
     rng = np.random.default_rng(0)
     n = 500
