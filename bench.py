@@ -612,8 +612,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the path shards by environment with no communication in the "
-              "forward pass; multi-GPU runs are not part of this build.", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the path shards by environment with no "
+              "communication in the forward pass, and the library has no multi-GPU launch.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -55,7 +55,7 @@ typedef enum fc_status {
   FC_ERR_RANGE = 4,       /* a numeric parameter is out of range (h, k, K) */
   FC_ERR_WORKSPACE = 5,   /* workspace NULL or smaller than fc_workspace_bytes */
   FC_ERR_HIP = 6,         /* a HIP runtime call failed; see fc_last_hip_error */
-  FC_ERR_UNSUPPORTED = 7, /* valid request this build does not implement */
+  FC_ERR_UNSUPPORTED = 7, /* valid request the library does not implement */
   FC_ERR_SCRATCH = 8      /* more scratch than fc_sdf_query_noalloc holds */
 } fc_status;
 
