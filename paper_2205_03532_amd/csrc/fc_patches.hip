@@ -25,8 +25,9 @@ __device__ __forceinline__ float dot3_nofma(float ax, float ay, float az, float 
 // xor 2, then the 8-lane and 16-lane mirrors (with every lane of a group
 // holding the group's result, a mirror pairs the two halves), which leaves
 // each 16-lane row's result in all its lanes; the four rows are then read as
-// scalars.  A 64-bit maximum takes the high words' maximum first, then the
-// low words of the lanes that hold it.  The result is the same in every lane.
+// scalars.  A 64-bit maximum takes the high words' maximum first, then, if
+// several lanes hold it, the low words of those lanes.  The result is the
+// same in every lane.
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp_u32(unsigned v) {
   return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
@@ -46,11 +47,6 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
   const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
   return umax(umax(a, b), umax(c, d));
-}
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  const unsigned hi = wave_max_u32((unsigned)(v >> 32));
-  const unsigned lo = wave_max_u32((unsigned)(v >> 32) == hi ? (unsigned)v : 0u);
-  return join64(lo, hi);
 }
 
 __device__ __forceinline__ int wave_sum_i32(int v) {
@@ -256,9 +252,16 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
     }
     for (;;) {
       {  // this wave's deepest remaining entry, to the exchange slot
-        const unsigned long long wbest = wave_max_u64(mk);
-        const unsigned long long own = __ballot(mk == wbest);
+        // the high words' maximum; when one lane holds it (the usual case)
+        // that lane's key is the maximum, else the low words decide
+        const unsigned hi = wave_max_u32((unsigned)(mk >> 32));
+        unsigned long long own = __ballot((unsigned)(mk >> 32) == hi);
+        if (__popcll(own) != 1) {
+          const unsigned lo = wave_max_u32((unsigned)(mk >> 32) == hi ? (unsigned)mk : 0u);
+          own = __ballot(mk == join64(lo, hi));
+        }
         const int ol = __ffsll((long long)own) - 1;  // the owner lane (keys are unique)
+        const unsigned long long wbest = join64((unsigned)__builtin_amdgcn_readlane((int)(unsigned)mk, ol), hi);
         const float wx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx), ol));
         const float wy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my), ol));
         const float wz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mz), ol));
