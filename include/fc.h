@@ -485,8 +485,10 @@ fc_status fc_bake_sdf_unculled(const void* table, int32_t n_tris, int32_t nx, in
 /* Load a launch-shape cache written by the autotuner: a JSON object
  * {"entries": [{"key": "<signature>", "block": B, "tile": T,
  * "persistent": P, "grid_mult": M, "xcd_remap": X}, ...]}.  Batches created afterwards whose
- * signature matches use that shape.  Returns the number of entries loaded,
- * or -1 if the file cannot be read or parsed. */
+ * signature matches use that shape.  Other members of the object (the
+ * tuner's "layouts" list, which the caller reads to choose a grid layout
+ * before converting its grids) are skipped.  Returns the number of entries
+ * loaded, or -1 if the file cannot be read or parsed. */
 int32_t fc_autotune_load(const char* json_path);
 
 /* Signature of a batch, the autotune cache key (NUL-terminated, at most
