@@ -87,7 +87,10 @@ __device__ __forceinline__ void wave_argmax(float& d, int& p) {
 //             similar to it (BinReduce) while finding its next deepest, and
 //             the patch is added with its member count summed by LDS
 //             atomics (AddPatch).  The per-wave records alternate between
-//             two LDS slots, so one barrier per patch suffices.
+//             two LDS slots, so one barrier per patch suffices.  A batch
+//             with at most 64 unassigned entries and room for a patch per
+//             entry (most batches after the first) runs the loop on wave 0
+//             alone, with no barrier.
 template <int DT, int LAYOUT>
 __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs P) {
   constexpr int kWaves = kPatchThreads / 64;
@@ -107,6 +110,7 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
   __shared__ uint4 s_red[2][kWaves];    // each wave's deepest entry: key (x, y), normal x, y (z: s_redz)
   __shared__ float s_redz[2][kWaves];
   __shared__ int s_members[2];          // a replaced patch's member count
+  __shared__ int s_np;                  // the patch count, for the waves that sat out a batch's loop
 
   const int e = blockIdx.x;
   const int gm = A.envs[e].gm;
@@ -124,6 +128,7 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
   for (int b0 = 0; b0 < m.n; b0 += kPatchBatch) {
     if (tid == 0) s_nc = 0;
     __syncthreads();
+    if (b0 > 0) np = s_np;  // written by thread 0 at the end of the previous batch
     // Generate
     {
       float px[kPatchVpt], py[kPatchVpt], pz[kPatchVpt];
@@ -223,8 +228,50 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
       }
       u = base;
     }
-    if (u == 0) continue;  // the same in every thread: nothing left for the loop
+    if (u == 0) {  // the same in every thread: nothing left for the loop
+      if (tid == 0) s_np = np;
+      continue;
+    }
     __syncthreads();
+    if ((u <= 64) & (np + u <= P.n_max)) {
+      // Few entries and no replacement possible (each pass adds one patch):
+      // wave 0 holds them all in one row and runs the loop alone, with no
+      // exchange or barrier per patch; the other waves go on to the next
+      // batch's barrier.  The same decisions as the four-wave loop.
+      if (wave == 0) {
+        unsigned long long k = lane < u ? s_ck[lane] : 0ull;
+        const float x = lane < u ? s_cn[lane][0] : 0.f, y = lane < u ? s_cn[lane][1] : 0.f,
+                    z = lane < u ? s_cn[lane][2] : 0.f;
+        for (;;) {
+          const unsigned hi = wave_max_u32((unsigned)(k >> 32));
+          unsigned long long own = __ballot((unsigned)(k >> 32) == hi);
+          if (__popcll(own) != 1) {
+            const unsigned lo = wave_max_u32((unsigned)(k >> 32) == hi ? (unsigned)k : 0u);
+            own = __ballot(k == join64(lo, hi));
+          }
+          const int ol = __ffsll((long long)own) - 1;  // the owner lane (keys are unique)
+          const unsigned long long best = join64((unsigned)__builtin_amdgcn_readlane((int)(unsigned)k, ol), hi);
+          if (best == 0ull) break;  // the same in every lane: the batch is done
+          const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), ol));
+          const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), ol));
+          const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z), ol));
+          // BinReduce and AddPatch (a free slot exists: np + u <= n_max)
+          const bool in = (k != 0ull) & ((k == best) | (dot3_nofma(bx, by, bz, x, y, z) >= cs));
+          k = in ? 0ull : k;
+          const int slot = np++;
+          if (in) atomicAdd(&s_pmem[slot], 1);
+          if (lane == 0) {
+            s_pn[slot][0] = bx;
+            s_pn[slot][1] = by;
+            s_pn[slot][2] = bz;
+            s_pkey[slot] = best;
+            s_pfound[slot] = (int)key_vidx(best);
+          }
+        }
+        if (tid == 0) s_np = np;
+      }
+      continue;
+    }
     // the loop: rows r = s * kWaves + wave of the packed entries in registers
     unsigned long long ek[kSlots];
     float ex[kSlots], ey[kSlots], ez[kSlots];
@@ -339,8 +386,10 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
       par ^= 1;
     }
     par ^= 1;
+    if (tid == 0) s_np = np;
   }
   __syncthreads();
+  np = m.n > 0 ? s_np : 0;
   // the patch list, each with its deepest member's record
   if (tid == 0) P.count[e] = np;
   const long long S = (long long)A.n_env * P.n_max;
