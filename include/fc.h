@@ -205,13 +205,22 @@ typedef struct fc_grads {
  *               tile and grid_mult then do not apply;
  *   grid_mult   workgroups per compute unit for persistent launches (1..32);
  *   xcd_remap   1: split the items into 8 contiguous ranges, one per XCD
- *               (each XCD has its own L2), for the forward and the adjoint. */
+ *               (each XCD has its own L2), for the forward and the adjoint;
+ *   wave_prio   wave priority in the kernels that run the adjoint's work
+ *               items (the adjoint, the one-pass query + adjoint, and
+ *               persistent = 3): 0 none; 1 (the default) a wave raises its
+ *               priority while it computes a vertex's cell and issues the
+ *               corner loads, which suits batches bound by the gather's
+ *               latency; 2 while it evaluates the gathered corners, which
+ *               suits batches whose evaluation dominates.  Scheduling only.
+ * fc_batch_create starts from {256, 1024, 0, 8, 0, 1}. */
 typedef struct fc_launch {
   int32_t block;
   int32_t tile;
   int32_t persistent;
   int32_t grid_mult;
   int32_t xcd_remap;
+  int32_t wave_prio;
 } fc_launch;
 
 /* ---- set-up ------------------------------------------------------------- */
@@ -484,7 +493,8 @@ fc_status fc_bake_sdf_unculled(const void* table, int32_t n_tris, int32_t nx, in
 
 /* Load a launch-shape cache written by the autotuner: a JSON object
  * {"entries": [{"key": "<signature>", "block": B, "tile": T,
- * "persistent": P, "grid_mult": M, "xcd_remap": X}, ...]}.  Batches created afterwards whose
+ * "persistent": P, "grid_mult": M, "xcd_remap": X, "wave_prio": W}, ...]}
+ * (xcd_remap defaults to 0, wave_prio to 1).  Batches created afterwards whose
  * signature matches use that shape.  Other members of the object (the
  * tuner's "layouts" list, which the caller reads to choose a grid layout
  * before converting its grids) are skipped.  Returns the number of entries

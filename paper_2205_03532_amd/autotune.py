@@ -9,7 +9,8 @@ shape's (the reduction is an integer max, so any difference is a bug), and
 records the fastest in a JSON cache keyed by the batch signature:
 
     {"entries": [{"key": "<signature>", "block": 256, "tile": 1024,
-                  "persistent": 2, "grid_mult": 8, "ms": 0.41}, ...]}
+                  "persistent": 2, "grid_mult": 8, "xcd_remap": 1,
+                  "wave_prio": 1, "ms": 0.41}, ...]}
 
 ``fc_autotune_load(path)`` makes later ``fc_batch_create`` calls with a
 matching signature start from that shape.
@@ -31,7 +32,11 @@ a layout-free key:
 
 The one-pass kernel's own tile (vertices per item) and block are not tuned:
 they order every per-env sum of the adjoint, so a different choice would
-change the gradients' rounding.
+change the gradients' rounding.  Its wave priority mode (``wave_prio``: none,
+raised while a wave issues its corner loads, or raised while it evaluates) is
+scheduling only, so every launch-shape entry also carries the mode with the
+fastest one-pass step (the default, 1, unless another is more than 1 % faster),
+its outputs checked bit-identical to the default mode's.
 """
 from __future__ import annotations
 
@@ -44,7 +49,7 @@ import numpy as np
 
 from . import fc
 
-DEFAULT = dict(block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=0)
+DEFAULT = dict(block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=0, wave_prio=1)
 
 
 def candidate_shapes():
@@ -54,8 +59,8 @@ def candidate_shapes():
             for persistent in (0, 1, 2):
                 for gm in ((8,) if persistent == 0 else (2, 4, 8, 16)):
                     for xr in (0, 1):
-                        out.append(dict(block=block, tile=block * vpt, persistent=persistent, grid_mult=gm,
-                                        xcd_remap=xr))
+                        out.append(dict(DEFAULT, block=block, tile=block * vpt, persistent=persistent,
+                                        grid_mult=gm, xcd_remap=xr))
     # env-chunked items (block, tile and grid_mult do not apply)
     for xr in (0, 1):
         out.append(dict(DEFAULT, persistent=3, xcd_remap=xr))
@@ -139,13 +144,27 @@ def save(entries, path, layouts=()):
 # (about the run-to-run spread of these timings), so noise does not flip it.
 LAYOUTS = ("brick", "slab", "linear")
 LAYOUT_MARGIN = 0.01
+# wave priority modes, the default first (the same margin applies)
+PRIOS = (1, 0, 2)
+
+
+def _pick(ms, default):
+    """default unless another choice is faster by more than LAYOUT_MARGIN;
+    then the fastest."""
+    fastest = min(ms, key=ms.get)
+    return fastest if ms[fastest] < (1.0 - LAYOUT_MARGIN) * ms[default] else default
 
 
 def pick_layout(step_ms):
     """The default layout unless another's step is faster by more than
     LAYOUT_MARGIN; then the fastest."""
-    fastest = min(step_ms, key=step_ms.get)
-    return fastest if step_ms[fastest] < (1.0 - LAYOUT_MARGIN) * step_ms[LAYOUTS[0]] else LAYOUTS[0]
+    return _pick(step_ms, LAYOUTS[0])
+
+
+def pick_prio(step_ms):
+    """The default wave priority mode unless another's step is faster by more
+    than LAYOUT_MARGIN; then the fastest."""
+    return _pick(step_ms, PRIOS[0])
 
 
 def layout_key(signature):
@@ -190,25 +209,51 @@ def time_step(batch, pose, k, reps, warmup):
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
 
+def _diff(snap, ref):
+    return [n for n in ref if not np.array_equal(snap[n].view(np.uint8), ref[n].view(np.uint8))]
+
+
+def tune_prio(batch, pose, k=1e4, reps=10, warmup=3, prios=PRIOS):
+    """Time the one-pass step under each wave priority mode (the batch's
+    launch shape otherwise kept); every mode's outputs must equal the first's
+    bit for bit.  Leaves the chosen mode set; returns (mode, {mode: ms})."""
+    shape = batch.get_launch()
+    ref, ms = None, {}
+    for p in prios:
+        batch.set_launch(**dict(shape, wave_prio=p))
+        snap = _step_snapshot(batch, pose, k)
+        if ref is None:
+            ref = snap
+        elif _diff(snap, ref):
+            raise RuntimeError(f"wave priority {p} changed the step's outputs: {_diff(snap, ref)}")
+        ms[p] = time_step(batch, pose, k, reps, warmup)
+    best = pick_prio(ms)
+    batch.set_launch(**dict(shape, wave_prio=best))
+    return best, ms
+
+
 def tune_layouts(w, layouts=LAYOUTS, k=1e4, reps=10, warmup=3, device="cuda:0", shapes=None, log=print):
-    """Per layout: a batch in spatial env order, its forward launch shape
-    tuned, its one-pass step timed; every layout's step outputs must equal the
-    first layout's bit for bit.  Returns (layout entry, launch entries)."""
+    """Per layout: a batch in spatial env order, its forward launch shape and
+    wave priority mode tuned, its one-pass step timed; every layout's step
+    outputs must equal the first layout's bit for bit.  Returns (layout entry,
+    launch entries)."""
     pose = fc.pose_tensor(w.pose, device)
     ref, step_ms, entries, sig = None, {}, [], None
     for lay in layouts:
         batch = fc.Batch.from_workload(w, device=device, layout=lay, env_order=fc.locality_order(w))
         best, _ = tune(batch, pose, shapes=shapes, reps=reps, warmup=warmup, log=lambda s: None)
-        entries.append(best)
         snap = _step_snapshot(batch, pose, k)
         if ref is None:
             ref = snap
-        elif not _same(snap, ref):
-            bad = [n for n in ref if not np.array_equal(snap[n].view(np.uint8), ref[n].view(np.uint8))]
-            raise RuntimeError(f"layout {lay} changed the step's outputs: {bad}")
-        step_ms[lay] = time_step(batch, pose, k, reps, warmup)
+        elif _diff(snap, ref):
+            raise RuntimeError(f"layout {lay} changed the step's outputs: {_diff(snap, ref)}")
+        prio, prio_ms = tune_prio(batch, pose, k, reps, warmup)
+        best = dict(best, wave_prio=prio, step_ms={str(p): v for p, v in prio_ms.items()})
+        entries.append(best)
+        step_ms[lay] = prio_ms[prio]
         sig = batch.signature()
-        log(f"  {lay}: forward {best['ms']:.4f} ms ({ {n: best[n] for n in DEFAULT} }), step {step_ms[lay]:.4f} ms")
+        log(f"  {lay}: forward {best['ms']:.4f} ms ({ {n: best[n] for n in DEFAULT} }), step {step_ms[lay]:.4f} ms "
+            f"(by wave priority: { {p: round(v, 4) for p, v in prio_ms.items()} })")
         del batch
     return dict(key=layout_key(sig), layout=pick_layout(step_ms), step_ms=step_ms), entries
 
@@ -234,10 +279,23 @@ def main(argv=None):
     ap.add_argument("--layout", default="brick", choices=["linear", "brick", "slab", "sparse"])
     ap.add_argument("--layouts", action="store_true",
                     help="also choose the dense layout (brick, slab, linear) by the one-pass step's time")
+    ap.add_argument("--prio", action="store_true",
+                    help="only choose the wave priority mode, keeping the launch shape the cache at --out holds")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     w = _workload(a.workload, a.dtype)
+    if a.prio:
+        if os.path.exists(a.out):
+            fc.fc_autotune_load(a.out)
+        batch = fc.Batch.from_workload(w, layout=a.layout, env_order=fc.locality_order(w))
+        sig = batch.signature()
+        old = next((e for e in _load(a.out).get("entries", []) if e["key"] == sig), batch.get_launch())
+        prio, prio_ms = tune_prio(batch, fc.pose_tensor(w.pose), reps=a.reps)
+        entry = dict(old, key=sig, wave_prio=prio, step_ms={str(p): v for p, v in prio_ms.items()})
+        save([entry], a.out)
+        print(json.dumps(entry), flush=True)
+        return 0
     if a.layouts:
         print(f"tuning the layout of {w.name} ({a.dtype})", flush=True)
         lay, entries = tune_layouts(w, reps=a.reps, log=lambda s: print(s, flush=True))
@@ -248,6 +306,8 @@ def main(argv=None):
     pose = fc.pose_tensor(w.pose)
     print(f"tuning {w.name} ({a.dtype}, {a.layout}): {batch.Q} queries", flush=True)
     best, _ = tune(batch, pose, reps=a.reps, log=lambda s: print(s, flush=True))
+    prio, prio_ms = tune_prio(batch, pose, reps=a.reps)
+    best = dict(best, wave_prio=prio, step_ms={str(p): v for p, v in prio_ms.items()})
     save([best], a.out)
     print(json.dumps(best), flush=True)
 

@@ -123,6 +123,7 @@ bool launch_valid(const fc_launch& l) {
   if (l.persistent < 0 || l.persistent > 3) return false;
   if (l.grid_mult < 1 || l.grid_mult > 32) return false;
   if (l.xcd_remap < 0 || l.xcd_remap > 1) return false;
+  if (l.wave_prio < 0 || l.wave_prio > 2) return false;
   return true;
 }
 
@@ -367,7 +368,7 @@ struct fc_batch {
   std::vector<float> dirs;
   std::vector<long long> qoff;
   long long Q = 0;
-  fc_launch launch{256, 1024, 0, 8, 0};
+  fc_launch launch{256, 1024, 0, 8, 0, 1};
   int num_cus = 256;
   int device = 0;  // the device current at creation: its tables live there
   int bwd_chunk = 0;  // envs per backward item (choose_bwd_chunk)
@@ -749,6 +750,7 @@ BwdArgs make_bwd(const fc_batch* b, const float* pose, float k, const float* ups
   a.k = k;
   a.per_env = out->verts_per_env ? 1 : 0;
   a.xcd = b->launch.xcd_remap;
+  a.prio = b->launch.wave_prio;
   a.Q = b->Q;
   a.loss = out->loss;
   a.d_pose = out->d_pose;
@@ -1479,9 +1481,10 @@ int32_t fc_autotune_load(const char* path) {
     const JVal* pe = jget(e, "persistent");
     const JVal* gm = jget(e, "grid_mult");
     const JVal* xr = jget(e, "xcd_remap");
+    const JVal* wp = jget(e, "wave_prio");
     if (!key || key->kind != JVal::STR || !bl || !ti || !pe || !gm) continue;
     fc_launch l{(int32_t)bl->num, (int32_t)ti->num, (int32_t)pe->num, (int32_t)gm->num,
-                xr ? (int32_t)xr->num : 0};
+                xr ? (int32_t)xr->num : 0, wp ? (int32_t)wp->num : 1};
     if (!launch_valid(l)) continue;
     g_tune[key->str] = l;
     ++loaded;

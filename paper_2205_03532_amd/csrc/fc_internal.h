@@ -170,7 +170,8 @@ struct BwdArgs {
   int n_env;
   float k;
   int per_env;
-  int xcd;  // XCD-contiguous item ranges
+  int xcd;   // XCD-contiguous item ranges
+  int prio;  // wave priority mode (fc_launch::wave_prio)
   long long Q;
   float* loss;
   float* d_pose;

@@ -739,7 +739,12 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     const float4 p0 = s_pose[c][0], p1 = s_pose[c][1], p2 = s_pose[c][2];
     return Rigid{p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, p0.w, p1.w, p2.w};
   };
+  // Wave priority (A.prio): 1 raises it while a wave computes addresses and
+  // issues its corner loads, so loads of waves that are ready to issue them
+  // go out ahead of other waves' arithmetic; 2 raises it while a wave
+  // evaluates.  Scheduling only: the results do not depend on it.
   const auto issue = [&](Stage& S, int c) {  // transform, locate, start the gather
+    if (A.prio == 1) __builtin_amdgcn_s_setprio(2);
     const Rigid P = pose_of(c);
 #pragma unroll
     for (int j = 0; j < V; ++j) {
@@ -749,8 +754,9 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     }
 #pragma unroll
     for (int j = 0; j < V; ++j) gather<DT, LAYOUT>(g, S.cl[j], S.cc[j]);
+    __builtin_amdgcn_s_setprio(0);
   };
-  const auto finish = [&](Stage& S, int c) {  // everything after the gather
+  const auto evaluate = [&](Stage& S, int c) {  // everything after the gather
     if constexpr (PROBE) {
       float sum = 0.f;
 #pragma unroll
@@ -855,6 +861,11 @@ __device__ __forceinline__ void backward_item(const BwdArgs& A, const QX& F, uns
     }
     if (lane < 8)
       A.pose_part[((long long)s_row[c] * NW + wave) * 8 + wave_sum8_slot(lane)] = red;
+  };
+  const auto finish = [&](Stage& S, int c) {
+    if (A.prio == 2) __builtin_amdgcn_s_setprio(2);
+    evaluate(S, c);
+    __builtin_amdgcn_s_setprio(0);
   };
   if constexpr (V <= 2) {
     Stage SA, SB;

@@ -84,7 +84,7 @@ class fc_grads(C.Structure):
 
 class fc_launch(C.Structure):
     _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("persistent", C.c_int32), ("grid_mult", C.c_int32),
-                ("xcd_remap", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("wave_prio", C.c_int32)]
 
 
 # every symbol include/fc.h declares, with its ctypes signature
@@ -148,6 +148,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2205_03532_amd.build` "
                                "(or __graft_entry__.build()); there is no CPU fallback")
+        # torch first: its HIP runtime is then already in the process and the
+        # library binds to that one, so streams and device pointers pass
+        # between the two (loaded the other way round, the library's first HIP
+        # call has failed with hipErrorNoDevice)
+        import torch  # noqa: F401
+
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
@@ -435,15 +441,15 @@ class Batch:
             raise RuntimeError(f"fc_batch_read_timing failed (hip error {lib().fc_last_hip_error()})")
         return np.array(ms[:n], dtype=np.float64), np.array(kid[:n], dtype=np.int32)
 
-    def set_launch(self, block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=0):
-        _check(lib().fc_batch_set_launch(self.handle, C.byref(fc_launch(block, tile, persistent, grid_mult,
-                                                                         xcd_remap))), "fc_batch_set_launch")
+    def set_launch(self, block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=0, wave_prio=1):
+        l = fc_launch(block, tile, persistent, grid_mult, xcd_remap, wave_prio)
+        _check(lib().fc_batch_set_launch(self.handle, C.byref(l)), "fc_batch_set_launch")
 
     def get_launch(self):
         l = fc_launch()
         _check(lib().fc_batch_get_launch(self.handle, C.byref(l)), "fc_batch_get_launch")
         return dict(block=l.block, tile=l.tile, persistent=l.persistent, grid_mult=l.grid_mult,
-                    xcd_remap=l.xcd_remap)
+                    xcd_remap=l.xcd_remap, wave_prio=l.wave_prio)
 
     def signature(self):
         buf = C.create_string_buffer(1024)

@@ -174,10 +174,15 @@ def test_autotune_cache_parse(L, tmp_path):
         {"key": "a", "block": 256, "tile": 1024, "persistent": 0, "grid_mult": 8},
         {"key": "b", "block": 128, "tile": 512, "persistent": 2, "grid_mult": 4},
         {"key": "c", "block": 256, "tile": 1024, "persistent": 3, "grid_mult": 8, "xcd_remap": 1},
+        {"key": "d", "block": 256, "tile": 1024, "persistent": 0, "grid_mult": 8, "wave_prio": 0},
+        {"key": "e", "block": 256, "tile": 1024, "persistent": 0, "grid_mult": 8, "wave_prio": 2,
+         "step_ms": {"1": 0.14, "0": 0.15, "2": 0.13}},
         {"key": "bad", "block": 100, "tile": 1024, "persistent": 0, "grid_mult": 8},
         {"key": "bad2", "block": 256, "tile": 1024, "persistent": 4, "grid_mult": 8},
+        {"key": "bad3", "block": 256, "tile": 1024, "persistent": 0, "grid_mult": 8, "wave_prio": 3},
+        {"key": "bad4", "block": 256, "tile": 1024, "persistent": 0, "grid_mult": 8, "wave_prio": -1},
     ]}))
-    assert L.fc_autotune_load(str(p).encode()) == 3
+    assert L.fc_autotune_load(str(p).encode()) == 5
     p.write_text("{not json")
     assert L.fc_autotune_load(str(p).encode()) == -1
     assert L.fc_autotune_load(b"/nonexistent/file.json") == -1

@@ -210,3 +210,63 @@ def test_layout_tuner_steps_are_bit_identical_across_layouts():
     assert lay["layout"] == autotune.pick_layout(lay["step_ms"])
     assert len(entries) == len(autotune.LAYOUTS) and len({e["key"] for e in entries}) == len(autotune.LAYOUTS)
     assert {autotune.layout_key(e["key"]) for e in entries} == {lay["key"]}
+
+
+@pytest.mark.parametrize("workload,layout", [("nutbolt", "brick"), ("nutbolt", "sparse"), ("mixed", "slab")])
+def test_wave_priority_modes_are_bit_identical(workload, layout):
+    """Every wave priority mode (none, raised while a wave issues its corner
+    loads, raised while it evaluates) gives the same outputs bit for bit: the
+    one-pass step (shared and per-env vertex gradients), the separate adjoint
+    and the env-chunked forward."""
+    torch = torch_gpu()
+    w = (W.subset(W.nut_bolt_workload(), range(40)) if workload == "nutbolt"
+         else W.subset(W.mixed_workload(), range(0, 4096, 32)))
+    b = fc.Batch.from_workload(w, layout=layout, env_order=fc.locality_order(w))
+    pose = fc.pose_tensor(w.pose)
+    shape = b.get_launch()
+    assert shape["wave_prio"] == 1
+    ref = None
+    for p in (1, 0, 2):
+        b.set_launch(**dict(shape, wave_prio=p))
+        assert b.get_launch()["wave_prio"] == p
+        res = [*onepass(b, pose), *onepass(b, pose, per_env=True, upstream=upstream_for(w.n_env, 5)),
+               *separate(b, pose)]
+        b.set_launch(**dict(shape, persistent=3, wave_prio=p))
+        o = b.new_contacts()
+        fc.fc_sdf_query(b, pose, fused_out=o)
+        torch.cuda.synchronize()
+        res.append(to_np(o))
+        if ref is None:
+            ref = res
+            assert int(res[0]["count"].sum()) > 0
+        else:
+            for x, y in zip(ref, res):
+                assert_same(x, y)
+    with pytest.raises(RuntimeError):
+        b.set_launch(**dict(shape, wave_prio=3))
+
+
+def test_cache_entry_sets_the_wave_priority(tmp_path):
+    """A loaded cache entry's wave_prio applies to batches created afterwards
+    with that signature; an entry without one gives the default (1)."""
+    import json
+
+    torch_gpu()
+    w = W.subset(W.nut_bolt_workload(), range(8))
+    b = fc.Batch.from_workload(w, layout="brick")
+    sig = b.signature()
+    del b
+    p = tmp_path / "c.json"
+    try:
+        for entry, want in ((dict(wave_prio=2), 2), ({}, 1), (dict(wave_prio=0), 0)):
+            p.write_text(json.dumps({"entries": [dict(key=sig, block=256, tile=1024, persistent=0, grid_mult=8,
+                                                      xcd_remap=1, **entry)]}))
+            assert fc.fc_autotune_load(str(p)) == 1
+            b = fc.Batch.from_workload(w, layout="brick")
+            assert b.get_launch() == dict(block=256, tile=1024, persistent=0, grid_mult=8, xcd_remap=1,
+                                          wave_prio=want)
+            del b
+    finally:  # later batches of this signature start from the library's default again
+        p.write_text(json.dumps({"entries": [dict(key=sig, block=256, tile=1024, persistent=0, grid_mult=8,
+                                                  xcd_remap=0, wave_prio=1)]}))
+        assert fc.fc_autotune_load(str(p)) == 1

@@ -55,6 +55,13 @@ def test_layout_choice_keeps_brick_within_the_margin():
     assert autotune.pick_layout({"brick": 1.0, "slab": 1.2, "linear": 0.5}) == "linear"
 
 
+def test_wave_priority_choice_keeps_the_default_within_the_margin():
+    assert autotune.PRIOS[0] == autotune.DEFAULT["wave_prio"] == 1
+    assert autotune.pick_prio({1: 1.0, 0: 0.995, 2: 1.01}) == 1
+    assert autotune.pick_prio({1: 1.0, 0: 1.02, 2: 0.97}) == 2
+    assert autotune.pick_prio({1: 1.0, 0: 0.9, 2: 0.97}) == 0
+
+
 def test_library_reads_a_cache_with_layout_entries(tmp_path):
     L = fc.lib()
     p = str(tmp_path / "c.json")
