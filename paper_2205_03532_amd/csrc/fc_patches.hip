@@ -91,6 +91,11 @@ __device__ __forceinline__ void wave_argmax(float& d, int& p) {
 //             with at most 64 unassigned entries and room for a patch per
 //             entry (most batches after the first) runs the loop on wave 0
 //             alone, with no barrier.
+// The waves of the workgroups sharing a compute unit take the SIMDs by
+// phase: the loop (a chain of short dependent steps) at the highest wave
+// priority, Assign next, Generate (the gather and evaluation, which the
+// others' gaps absorb) last.  Scheduling only; the results do not depend
+// on it.
 template <int DT, int LAYOUT>
 __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs P) {
   constexpr int kWaves = kPatchThreads / 64;
@@ -126,6 +131,7 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
   int par = 0;  // LDS record slot of the current patch step
 
   for (int b0 = 0; b0 < m.n; b0 += kPatchBatch) {
+    __builtin_amdgcn_s_setprio(0);  // Generate
     if (tid == 0) s_nc = 0;
     __syncthreads();
     if (b0 > 0) np = s_np;  // written by thread 0 at the end of the previous batch
@@ -167,6 +173,7 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
       }
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(1);  // Assign
     const int nc = s_nc;
     // Assign, against the patch list as it stands.  The first patch of
     // largest dot over all patches is the patch of largest dot among the
@@ -233,6 +240,7 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
       continue;
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(2);  // the loop
     if ((u <= 64) & (np + u <= P.n_max)) {
       // Few entries and no replacement possible (each pass adds one patch):
       // wave 0 holds them all in one row and runs the loop alone, with no
@@ -388,6 +396,7 @@ __global__ __launch_bounds__(kPatchThreads) void k_patches(FwdArgs A, PatchArgs 
     par ^= 1;
     if (tid == 0) s_np = np;
   }
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
   np = m.n > 0 ? s_np : 0;
   // the patch list, each with its deepest member's record
